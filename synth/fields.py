@@ -1,0 +1,136 @@
+"""Seeded synthetic initial fields, permittivity maps, sources and receivers.
+
+Initial conditions follow the leapfrog convention of the paper's scheme
+(Section 5, eq. 19 and eq. 21): E is given at t = 0 and H at t = -dt/2.
+Field layouts returned here are plain numpy arrays in the caller's (original)
+node order: 2D TMz -> E [N, 1] (Ez), H [N, 2] (Hx, Hy); 3D -> E [N, 3],
+H [N, 3].
+
+The closed-form cavity modes are standard solutions of the vacuum curl
+equations (eq. 2) with perfectly conducting walls; with them the same
+functions also give the exact field at any later time, which tests use as the
+analytic reference.
+"""
+import math
+import numpy as np
+
+from . import rng
+
+
+def consts(eps0=1.0, mu0=1.0):
+    c0 = 1.0 / math.sqrt(eps0 * mu0)
+    eta0 = math.sqrt(mu0 / eps0)
+    return c0, eta0
+
+
+def tm_mode_2d(xyz, t_e, t_h, m=1, n=1, eps0=1.0, mu0=1.0):
+    """TM_mn mode of the PEC unit square: Ez at time t_e, (Hx, Hy) at t_h."""
+    c0, _ = consts(eps0, mu0)
+    w = c0 * math.pi * math.hypot(m, n)
+    x, y = xyz[:, 0], xyz[:, 1]
+    sx, cx = np.sin(m * math.pi * x), np.cos(m * math.pi * x)
+    sy, cy = np.sin(n * math.pi * y), np.cos(n * math.pi * y)
+    E = (sx * sy * math.cos(w * t_e))[:, None]
+    Hx = -(n * math.pi / (mu0 * w)) * sx * cy * math.sin(w * t_h)
+    Hy = (m * math.pi / (mu0 * w)) * cx * sy * math.sin(w * t_h)
+    return E, np.stack([Hx, Hy], axis=1), w
+
+
+def tm111_cube(xyz, t_e, t_h, eps0=1.0, mu0=1.0):
+    """TM_111 mode of the PEC unit cube: E at t_e, H at t_h."""
+    c0, _ = consts(eps0, mu0)
+    w = c0 * math.pi * math.sqrt(3.0)
+    p = math.pi
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    sx, cx = np.sin(p * x), np.cos(p * x)
+    sy, cy = np.sin(p * y), np.cos(p * y)
+    sz, cz = np.sin(p * z), np.cos(p * z)
+    ce = math.cos(w * t_e)
+    sh = math.sin(w * t_h)
+    E = np.stack([-0.5 * cx * sy * sz * ce, -0.5 * sx * cy * sz * ce, sx * sy * cz * ce], axis=1)
+    a = 3.0 * p / (2.0 * mu0 * w)
+    H = np.stack([-a * sx * cy * cz * sh, a * cx * sy * cz * sh, np.zeros_like(x)], axis=1)
+    return E, H, w
+
+
+def gaussian_pulse(xyz, centre, sigma):
+    """Ez = exp(-|x - centre|^2 / (2 sigma^2)), H = 0 (2D TMz)."""
+    d2 = ((xyz - np.asarray(centre)[None, :]) ** 2).sum(axis=1)
+    E = np.exp(-d2 / (2.0 * sigma * sigma))[:, None]
+    return E, np.zeros((xyz.shape[0], 2))
+
+
+def _wrap(u, L):
+    """Signed distance along a periodic axis into [-L/2, L/2)."""
+    return u - L * np.floor(u / L + 0.5)
+
+
+def periodic_plane_pulse(xyz, t_e, t_h, L=200.0, sigma=30.0, phi=0.0, eps0=1.0,
+                         mu0=1.0, images=2):
+    """Plane Gaussian pulse on the periodic square [0, L]^2 (eq. 21, eq. 27).
+
+    Travels along (cos phi, sin phi) at c0, centred on the line
+    cos(phi) x + sin(phi) y = L/2 at t = 0.  H = (sin phi, -cos phi) E / eta0,
+    which is the d'Alembert solution (eq. 22) for phi = 0.  The field is the
+    sum over ``images`` periodic copies on each side along the propagation
+    direction (one period L along x for phi = 0).
+    """
+    c0, eta0 = consts(eps0, mu0)
+    cp, sp = math.cos(phi), math.sin(phi)
+    s = cp * xyz[:, 0] + sp * xyz[:, 1]
+
+    def prof(t):
+        acc = np.zeros_like(s)
+        for k in range(-images, images + 1):
+            u = s - 0.5 * L - c0 * t + k * L
+            acc += np.exp(-u * u / (2.0 * sigma * sigma))
+        return acc
+
+    E = prof(t_e)[:, None]
+    g = prof(t_h)
+    H = np.stack([sp * g / eta0, -cp * g / eta0], axis=1)
+    return E, H
+
+
+def eps_r_smooth(xyz, seed=5, stream=2, n_modes=16, kmax=4, amp=0.5):
+    """eps_r = 1 + amp * s(x) / max|s|, s = sum of 16 seeded cosine modes.
+
+    s(x) = sum_q a_q cos(2 pi k_q . x + phi_q), k_q integer with |k_q|_inf <= kmax
+    (not both zero), a_q ~ U(-1, 1), phi_q ~ U(0, 2 pi).
+    """
+    d = xyz.shape[1]
+    q = np.arange(n_modes, dtype=np.uint64)
+    per = np.uint64(d + 2)
+    ks = []
+    for k in range(d):
+        u = rng.uniform(seed, stream, q * per + np.uint64(k))
+        ks.append(np.floor(u * (2 * kmax + 1)).astype(np.int64) - kmax)
+    K = np.stack(ks, axis=1)
+    zero = (K == 0).all(axis=1)
+    K[zero, 0] = 1
+    a = rng.uniform_range(seed, stream, q * per + np.uint64(d), -1.0, 1.0)
+    ph = rng.uniform_range(seed, stream, q * per + np.uint64(d + 1), 0.0, 2 * math.pi)
+    s = np.zeros(xyz.shape[0])
+    for j in range(n_modes):
+        s += a[j] * np.cos(2 * math.pi * (xyz @ K[j].astype(np.float64)) + ph[j])
+    return 1.0 + amp * s / np.abs(s).max()
+
+
+def seeded_points(n, lo, hi, seed, stream=1, d=2):
+    """n points uniform in the box [lo, hi]^d (source / receiver positions)."""
+    c = np.arange(n * d, dtype=np.uint64)
+    return rng.uniform_range(seed, stream, c, lo, hi).reshape(n, d)
+
+
+def nearest_node(xyz, pts):
+    """Index of the node closest to each point (lowest index on ties)."""
+    out = np.empty(pts.shape[0], dtype=np.int64)
+    for k, p in enumerate(pts):
+        d2 = ((xyz - p[None, :]) ** 2).sum(axis=1)
+        out[k] = int(np.argmin(d2))
+    return out
+
+
+def gaussian_wavelet(t, t0, tau):
+    """Time profile of the soft source: exp(-(t - t0)^2 / (2 tau^2))."""
+    return np.exp(-((np.asarray(t) - t0) ** 2) / (2.0 * tau * tau))
