@@ -1,0 +1,253 @@
+"""Benchmark of the meshless FDTD hot path on one MI355X.
+
+Default workload: the 2D TMz PEC unit-square cavity on ~1.0M Poisson-disk
+nodes (h ~ 1e-3), RBF-FD curl weights with n = 25, m = 4, hyperviscosity
+Delta^3 (n_hv = 57), Gaussian pulse (sigma = 20 h) at the centre, FP32 fields
+and weights.  A step is one full leapfrog step (H update + E update, eq. 19)
+over all nodes; inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line.  Besides the headline FP32 node-steps/s it reports the
+FP64 rate on the same nodes, the FP32-vs-FP64 relative L2 difference after the
+workload's 10^4 steps, the K = 64 batched rate (250k-node jittered grid), the
+roofline of the dominant kernel (the H update) and the FP64 CPU oracle timed on
+a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "node-steps/s (all field comps) + % HBM peak; FP32/batched vs FP64 at L2 err"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_bytes_half(n, nh, d, sw, sf, fe, fh, which):
+    """Algorithmic bytes per node of one half update (int32 union ELL).
+
+    Index list (n_hv entries) + curl (d n) and HV (n_hv) weights + fields:
+    the H update reads E and H and writes H, the E update reads E and H and
+    writes E.  Both halves sum to the per-node-step figure
+    2 n_hv s_i + 2 (d n + n_hv) s_w + 3 (F_E + F_H) s_f.
+    """
+    ns = max(n, nh)
+    fields = (fe + 2 * fh) if which == 0 else (2 * fe + fh)
+    return ns * 4 + (d * n + nh) * sw + fields * sf
+
+
+def time_halves(s, st, reps, torch):
+    """Average duration of each half-update kernel, HIP events on the library's stream."""
+    stream = torch.cuda.current_stream()
+    out = []
+    for which in (0, 1):
+        s.half(st, which)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            s.half(st, which)
+        e1.record(stream)
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1) / reps * 1e-3)
+    return out
+
+
+def cpu_baseline(w, seconds=15.0):
+    """FP64 oracle on a bounded sample: the nodes in a centred sub-square."""
+    import numpy as np
+    from oracle import setup as osetup, step as ostep
+    from synth import configs
+    half = 0.05
+    sel = np.all(np.abs(w.xyz - 0.5) <= half, axis=1)
+    sub = configs.Workload("sample", w.dim, w.xyz[sel].copy(), np.zeros(int(sel.sum()), np.uint8), w.h, w.n, w.m,
+                           w.alpha, w.n_hv, w.chat, 1, lo=(0.5 - half, 0.5 - half), hi=(0.5 + half, 0.5 + half))
+    sub.E0, sub.H0 = w.E0[sel], w.H0[sel]
+    t0 = time.time()
+    oh, oe = osetup.operators(sub)
+    t_setup = time.time() - t0
+    gamma = ostep.hv_gamma(sub.hv_c, sub.alpha, sub.h)
+    keep = np.ones((sub.N, 1))
+    t0 = time.time()
+    ostep.run(sub.E0, sub.H0, oh, oe, sub.dt, 2, gamma, sub.dt, keep)
+    per = max((time.time() - t0) / 2, 1e-4)
+    T = max(2, int(seconds / per))
+    t0 = time.time()
+    ostep.run(sub.E0, sub.H0, oh, oe, sub.dt, T, gamma, sub.dt, keep)
+    dt = time.time() - t0
+    return {"value": sub.N * T / dt, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 numpy oracle, {sub.N} nodes of the same node set (centred 0.1 x 0.1 "
+                      f"sub-square, same n, m, n_hv), {T} steps in {dt:.1f} s (set-up {t_setup:.1f} s untimed)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64", "bf16"])
+    ap.add_argument("--scale", type=float, default=1.0, help="node-count scale of the workload (1 = 1M)")
+    ap.add_argument("--accuracy-steps", type=int, default=10000)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip FP64, accuracy and batched legs")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this "
+              f"build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from synth import configs
+    from paper_2508_18205_amd import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    w = configs.pulse_2d(scale=args.scale)
+    t_gen = time.time() - t0
+    log(f"workload: N={w.N} h={w.h:.3e} n={w.n} m={w.m} alpha={w.alpha} n_hv={w.n_hv} (generated in {t_gen:.1f} s)")
+
+    def setup(prec):
+        torch.cuda.synchronize()
+        t = time.time()
+        s = Solver.from_workload(w, precision=prec)
+        torch.cuda.synchronize()
+        return s, time.time() - t
+
+    s, t_setup = setup(args.precision)
+    st = s.state(w.E0, w.H0)
+    log(f"setup ({args.precision}): {t_setup:.2f} s")
+    variant = None
+    if not args.no_tune:
+        variant = s.autotune(st, reps=10)
+        st = s.state(w.E0, w.H0)
+        log(f"tuned variant: {variant}")
+    if args.copy_probe_mib:
+        a = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+
+    s.run(st, args.warmup, use_graph=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t_wall = time.time()
+    e0.record(stream)
+    s.run(st, args.steps, use_graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.time() - t_wall
+    elapsed = e0.elapsed_time(e1) * 1e-3
+    value = w.N * args.steps / elapsed
+    log(f"timed {args.steps} steps: {elapsed * 1e3:.2f} ms ({value:.4e} node-steps/s; wall {t_wall * 1e3:.1f} ms)")
+
+    # roofline of the dominant kernel (H update) from HIP events on the same stream
+    th, te = time_halves(s, st, args.kernel_reps, torch)
+    sw = 8 if args.precision == "f64" else 4
+    sf = {"f64": 8, "f32": 4, "bf16": 2}[args.precision]
+    bh = alg_bytes_half(w.n, w.n_hv, w.dim, sw, sf, 1, 2, 0) * w.N
+    be = alg_bytes_half(w.n, w.n_hv, w.dim, sw, sf, 1, 2, 1) * w.N
+    gbs_h = bh / th / 1e9
+    gbs_e = be / te / 1e9
+    log(f"H update {th * 1e6:.1f} us -> {gbs_h:.0f} GB/s ; E update {te * 1e6:.1f} us -> {gbs_e:.0f} GB/s")
+    dominant = "H" if th >= te else "E"
+    ach = gbs_h if dominant == "H" else gbs_e
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_h2<float,float> (H update)" if dominant == "H" else "k_e2<float,float> (E update)",
+            "alg_bytes_per_launch": int(bh if dominant == "H" else be),
+            "avg_launch_us": round((th if dominant == "H" else te) * 1e6, 2),
+            "other_half": {"achieved": round(gbs_e if dominant == "H" else gbs_h, 1),
+                           "avg_launch_us": round((te if dominant == "H" else th) * 1e6, 2)}}
+
+    extras = {}
+    if not args.no_extras:
+        # FP64 rate on the same nodes, and FP32 vs FP64 after the workload's steps
+        s64, t64 = setup("f64")
+        st64 = s64.state(w.E0, w.H0)
+        s64.run(st64, args.warmup, use_graph=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        s64.run(st64, args.steps, use_graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        v64 = w.N * args.steps / (e0.elapsed_time(e1) * 1e-3)
+        extras["fp64"] = {"value": v64, "unit": "node-steps/s", "setup_s": round(t64, 2)}
+        T = args.accuracy_steps
+        a32 = s.state(w.E0, w.H0)
+        a64 = s64.state(w.E0, w.H0)
+        r32 = s.run(a32, T, energy_every=max(1, T // 20), use_graph=True)
+        r64 = s64.run(a64, T, energy_every=max(1, T // 20), use_graph=True)
+        E32, E64 = s.E_original(a32), s64.E_original(a64)
+        H32, H64 = s.H_original(a32), s64.H_original(a64)
+
+        def rl2(x, y):
+            ny = np.linalg.norm(y)
+            return float(np.linalg.norm(x - y) / ny) if ny > 0 and np.isfinite(ny) else float("nan")
+
+        u64 = r64["energy"] / r64["energy"][0]
+        extras["accuracy"] = {
+            "steps": T, "reference": "GPU FP64 path (pinned to the FP64 oracle at 1e-12 on smaller cases)",
+            "fp32_vs_fp64_rel_l2_E": rl2(E32, E64), "fp32_vs_fp64_rel_l2_H": rl2(H32, H64),
+            "fp64_energy_ratio_max": float(np.nanmax(u64)), "fp64_energy_ratio_end": float(u64[-1]),
+            "fp64_finite": bool(np.isfinite(E64).all())}
+        log(f"accuracy after {T} steps: {extras['accuracy']}")
+        del s64, st64, a64
+        torch.cuda.empty_cache()
+        # K = 64 fields sharing one weight set (250k-node jittered grid)
+        wb = configs.batched_2d(scale=1.0, K=64)
+        sb = Solver.from_workload(wb, precision="f32", K=64)
+        stb = sb.state_batched(wb.E0_batch, np.zeros((64, wb.N, 2)))
+        sb.run(stb, 20, use_graph=True)
+        torch.cuda.synchronize()
+        kb = 200
+        e0.record(stream)
+        sb.run(stb, kb, use_graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tb = e0.elapsed_time(e1) * 1e-3
+        extras["batched"] = {"value": wb.N * 64 * kb / tb, "unit": "field-node-steps/s", "K": 64, "N": wb.N,
+                             "steps": kb, "node_steps_per_s": wb.N * kb / tb,
+                             "alg_bytes_per_field_node_step": 50.0,
+                             "hbm_frac_at_50B": round(wb.N * 64 * kb / tb * 50.0 / (HBM_PEAK_GBS * 1e9), 4)}
+        log(f"batched: {extras['batched']}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w)
+        log(f"cpu baseline: {cpu}")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"pulse_2d: 2D TMz PEC unit square, {w.N} Poisson-disk nodes (h={w.h:.3e}), "
+                               f"RBF-FD n={w.n} m={w.m}, hyperviscosity alpha={w.alpha} n_hv={w.n_hv}, "
+                               f"Gaussian pulse sigma=20h, {args.precision} fields and weights",
+                   "N": w.N, "n": w.n, "m": w.m, "alpha": w.alpha, "n_hv": w.n_hv, "setup_s": round(t_setup, 2),
+                   "variant": variant},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    line.update(extras)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,273 @@
+/*
+ * rbffd.h -- C ABI of the MI355X (gfx950) meshless FDTD library.
+ *
+ * The library advances Maxwell's curl equations on scattered nodes with the
+ * stabilised interleaved leapfrog of Kolar-Pozun & Kosec, "An RBF-based
+ * method for computational electromagnetics with reduced numerical
+ * dispersion" (arXiv 2508.18205), Section 5, eq. 19, using precomputed local
+ * RBF differentiation weights (Section 4, eq. 9-15) for the curl and the
+ * hyperviscosity operator (Section 5.1).
+ *
+ * Conventions shared by every call
+ *  - Return value: RBFFD_OK (0) or a negative RBFFD_E* code; the plan keeps a
+ *    human-readable message (rbffd_last_error).  Nothing throws across the ABI.
+ *  - Memory: the CALLER owns all device memory.  rbffd_plan_sizes reports how
+ *    many bytes each buffer needs; the library never allocates device memory.
+ *    Host pointers are marked _host, everything else is device memory.
+ *  - Streams: every device call is asynchronous on the hipStream_t passed as
+ *    `void* stream` (NULL = the null stream).  Calls that return host data
+ *    synchronise that stream before returning.
+ *  - Node order: device state arrays are in the plan's INTERNAL order (the
+ *    node reordering chosen in rbffd_params.reorder).  rbffd_get_perm and
+ *    rbffd_permute convert to and from the caller's (original) order.
+ *  - Threading: a plan may be used by one host thread at a time.
+ */
+#ifndef RBFFD_H
+#define RBFFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define RBFFD_OK          0
+#define RBFFD_EINVAL     -1   /* bad argument or parameter combination       */
+#define RBFFD_ESIZE      -2   /* a size or count exceeds a supported maximum */
+#define RBFFD_ESINGULAR  -3   /* a local weight system is singular           */
+#define RBFFD_EHIP       -4   /* a HIP runtime call failed                   */
+#define RBFFD_EUNSTABLE  -5   /* NaN/Inf or energy above the run threshold   */
+#define RBFFD_ESTATE     -6   /* call out of order (e.g. step before weights)*/
+#define RBFFD_ENOTSUP    -7   /* feature not supported for this plan         */
+
+/* ---- enumerations ------------------------------------------------------ */
+#define RBFFD_MODE_FD     0   /* RBF-FD curl weights, eq. 13 (collocated)      */
+#define RBFFD_MODE_VFD    1   /* RBF-VFD central virtual difference, eq. 15    */
+#define RBFFD_MODE_STAG2  2   /* E and H on two node sets, RBF-FD (not the
+                                 paper's choice; cross-set curl stencils)     */
+#define RBFFD_BC_PEC      0   /* perfectly conducting walls on flagged nodes  */
+#define RBFFD_BC_PERIODIC 1   /* periodic box [lo, hi) (minimum image)        */
+#define RBFFD_ORDER_NONE   0
+#define RBFFD_ORDER_MORTON 1
+#define RBFFD_ORDER_RCM    2
+#define RBFFD_F64  0
+#define RBFFD_F32  1
+#define RBFFD_BF16 2          /* field storage only; arithmetic in FP32       */
+
+/* Which operator rbffd_get_weights / rbffd_set_weights address.  For the
+ * two-set variant the *_H operators are the ones applied in the H update
+ * (centres on the H set) and *_E in the E update. */
+#define RBFFD_OP_CURL_H 0     /* [N_target][dim][n]  first-derivative weights */
+#define RBFFD_OP_HV_H   1     /* [N_target][n_hv]    Delta^alpha weights      */
+#define RBFFD_OP_CURL_E 2
+#define RBFFD_OP_HV_E   3
+
+/* Which stencil rbffd_get_stencils returns (internal labels). */
+#define RBFFD_ST_UNION   0    /* collocated: [N][n_stencil], n_stencil = max(n, n_hv) */
+#define RBFFD_ST_CURL_H  1    /* two-set: [N_H][n] indices into the E set     */
+#define RBFFD_ST_HV_H    2    /* two-set: [N_H][n_hv] indices into the H set  */
+#define RBFFD_ST_CURL_E  3    /* two-set: [N_E][n] indices into the H set     */
+#define RBFFD_ST_HV_E    4    /* two-set: [N_E][n_hv] indices into the E set  */
+
+/* ---- parameters -------------------------------------------------------- */
+/* Every parameter of the method (Section 4.3, Section 5, Section 5.1). */
+typedef struct rbffd_params {
+    int32_t dim;        /* 2 = TMz (Ez, Hx, Hy; eq. 3), 3 = full curl equations   */
+    int32_t mode;       /* RBFFD_MODE_*                                           */
+    int32_t n;          /* curl stencil size (n nearest nodes, eq. 11)            */
+    int32_t m;          /* curl monomial degree (eq. 8)                           */
+    int32_t phs_k;      /* curl PHS exponent, phi(r) = r^phs_k (odd, >= 3)         */
+    int32_t hv_alpha;   /* hyperviscosity power alpha (0 = none)                  */
+    int32_t n_hv;       /* HV stencil size; 0 = 2 * C(2 alpha + dim, dim) + 1      */
+    int32_t bc;         /* RBFFD_BC_*                                             */
+    int32_t reorder;    /* RBFFD_ORDER_*                                          */
+    int32_t wdtype;     /* stored weight precision for the step: F64 or F32        */
+    int32_t fdtype;     /* field storage: F64, F32 or BF16 (BF16 needs F32 weights)*/
+    int32_t K;          /* independent fields per batch (1 = single field; 2D)    */
+    int32_t adjoint;    /* nonzero: also build transposed operators (2D, K = 1)   */
+    int32_t reserved;
+    double vfd_sigma;   /* RBF-VFD virtual spacing delta = vfd_sigma * h          */
+    double hv_c;        /* c of gamma = c (-1)^(alpha-1) h^(2 alpha), units 1/time */
+    double h;           /* nominal node spacing of the E set                      */
+    double h_h;         /* nominal spacing of the H set (two-set only; 0 = h)     */
+    double dt;          /* time step; 0 = h / (10 sqrt(2) c0)                     */
+    double eps0, mu0;   /* vacuum constants (c0 = 1/sqrt(eps0 mu0))               */
+    double lo[3], hi[3];/* bounding box; the period for RBFFD_BC_PERIODIC         */
+} rbffd_params;
+
+/* Sizes of every caller-owned buffer, in bytes, plus derived constants. */
+typedef struct rbffd_sizes {
+    int64_t N;               /* nodes of the E set (= all nodes when collocated) */
+    int64_t N_h;             /* nodes of the H set (= N when collocated)         */
+    int32_t n_stencil;       /* collocated union stencil width max(n, n_hv)      */
+    int32_t n_hv;            /* effective HV stencil size                        */
+    int32_t fe, fh;          /* values per node in E and H buffers (2D: 1, 2;
+                                3D: 4, 4 -- x, y, z and one unused pad value)    */
+    int32_t field_elem;      /* bytes per stored field value (8, 4 or 2)         */
+    int32_t K;
+    int64_t arena_bytes;     /* persistent device arena (weights, stencils, ...) */
+    int64_t workspace_bytes; /* scratch needed by rbffd_weights and rbffd_run    */
+    int64_t e_bytes;         /* one E buffer: N * fe * K * field_elem            */
+    int64_t h_bytes;         /* one H buffer: N_h * fh * K * field_elem          */
+    int64_t adjoint_ws_bytes;/* scratch of rbffd_adjoint excluding its segment   */
+    double dt;               /* effective time step                              */
+    double gamma;            /* effective hyperviscosity strength                */
+} rbffd_sizes;
+
+typedef struct rbffd_plan rbffd_plan;
+
+/* Field state.  E[cur], H[cur] hold (E^n, H^n) with H^n = H(t_{n - 1/2});
+ * the other buffer of each pair is overwritten by the next step, after which
+ * cur flips.  eps_r: NULL for eps_r = 1 everywhere, else [N] per-node relative
+ * permittivity in internal order, double for F64 fields and float otherwise. */
+typedef struct rbffd_fields {
+    void* E[2];
+    void* H[2];
+    int32_t cur;
+    int32_t reserved;
+    const void* eps_r;
+} rbffd_fields;
+
+/* Forward run (rbffd_run).  All arrays are device memory.
+ *  - energy_out [floor((T-1)/energy_every) + 1] double: U^n of eq. 20 for
+ *    n = 0, energy_every, ... (computed inside step n from E^n and the
+ *    average of H^n and H^{n+1}); NULL or energy_every = 0 disables.
+ *  - soft sources: after the E bracket of step n, E (Ez in 2D) at node
+ *    src_node[s] gains src_amp[s] * src_wave[n * n_src + s]; not scaled by
+ *    eps_r; PEC nodes stay zero.  (2D, K = 1.)
+ *  - receivers: traces[n * n_rcv + r] = E^{n+1} at rcv_node[r] (Ez in 2D).
+ *  - checkpoints: if ckpt != NULL the state (E^n, H^n) is copied to slot
+ *    n / ckpt_every for every n multiple of ckpt_every, n < T; one slot is
+ *    e_bytes + h_bytes long (E first).
+ *  - use_graph: capture the step loop in a HIP graph and replay it.
+ *  - unstable_threshold: > 0 makes the run fail with RBFFD_EUNSTABLE if an
+ *    energy sample is NaN or exceeds threshold * energy_out[0].
+ * The plan's precision templates apply; src_amp, src_wave are double for F64
+ * fields and float otherwise; traces have the same type. */
+typedef struct rbffd_run_args {
+    int32_t T;
+    int32_t energy_every;
+    double* energy_out;
+    int32_t n_src;
+    int32_t n_rcv;
+    const int32_t* src_node;
+    const void* src_amp;
+    const void* src_wave;
+    const int32_t* rcv_node;
+    void* traces;
+    void* ckpt;
+    int32_t ckpt_every;
+    int32_t use_graph;
+    double unstable_threshold;
+    int32_t step0;           /* global index of the first step (source time)    */
+    int32_t reserved;
+} rbffd_run_args;
+
+/* Discrete adjoint of a forward run (2D TMz, K = 1, collocated).
+ * ckpt holds the checkpoints written by a forward run with the same T, ckpt_every
+ * (slot 0 = the initial state).  grad_traces [T][n_rcv] = dJ/dtraces (same type
+ * as the fields).  Outputs (device double, overwritten): grad_eps [N] =
+ * dJ/deps_r (internal order), grad_amp [n_src] = dJ/dsrc_amp.  seg_buf must
+ * hold (ckpt_every + 1) E buffers; workspace must hold adjoint_ws_bytes. */
+typedef struct rbffd_adjoint_args {
+    int32_t T;
+    int32_t ckpt_every;
+    const void* ckpt;
+    int32_t n_src;
+    int32_t n_rcv;
+    const int32_t* src_node;
+    const void* src_amp;
+    const void* src_wave;
+    const int32_t* rcv_node;
+    const void* grad_traces;
+    double* grad_eps;
+    double* grad_amp;
+    void* seg_buf;
+    void* workspace;
+} rbffd_adjoint_args;
+
+/* ---- plan ---------------------------------------------------------------
+ * Host-only: validates the parameters (n > M_m, n_hv > M_{2 alpha}, stencils
+ * no larger than the node set, supported sizes) and copies the node data.
+ * xyz_host [N][dim] doubles, flags_host [N] bytes (bit 2k / 2k+1 = node on
+ * the low / high wall normal to axis k; ignored for periodic boxes).  For
+ * RBFFD_MODE_STAG2 pass the H set in N_h / xyzH_host / flagsH_host, else 0
+ * and NULL.  On success *out owns a new plan (free with rbffd_plan_destroy). */
+int rbffd_plan_create(const rbffd_params* p, int64_t N, const double* xyz_host,
+                      const uint8_t* flags_host, int64_t N_h, const double* xyzH_host,
+                      const uint8_t* flagsH_host, rbffd_plan** out);
+int rbffd_plan_sizes(const rbffd_plan* plan, rbffd_sizes* out);
+void rbffd_plan_destroy(rbffd_plan* plan);
+const char* rbffd_strerror(int code);
+const char* rbffd_last_error(const rbffd_plan* plan);
+
+/* ---- set-up on the GPU (computed once, reused every step: Section 5) -----
+ * arena: arena_bytes of device memory kept by the plan until destroyed or
+ * re-set; workspace: workspace_bytes of scratch (free to reuse afterwards).
+ * Runs node reordering, exact kNN stencils, the FP64 local weight systems
+ * (eq. 9 with eq. 13 / eq. 15 right-hand sides, HV by RBF-FD of Delta^alpha
+ * with phi = r^(2 alpha + 1), m = 2 alpha) and packs them for the step.
+ * RBFFD_ESINGULAR: a local system had a zero pivot (node named in the message). */
+int rbffd_weights(rbffd_plan* plan, void* arena, void* workspace, void* stream);
+
+/* ---- parity / inspection I/O (host buffers; synchronise the stream) ------ */
+/* perm_host[p] = original index of internal node p (set 0 = E, 1 = H). */
+int rbffd_get_perm(const rbffd_plan* plan, int32_t set, int32_t* perm_host, void* stream);
+/* which = RBFFD_ST_*: stencil rows of internal node p, nearest first, ties by
+ * original index, as internal labels of the source set. */
+int rbffd_get_stencils(const rbffd_plan* plan, int32_t which, int32_t* out_host, void* stream);
+/* Unfolded FP64 weights in internal order (layout of RBFFD_OP_*). */
+int rbffd_get_weights(const rbffd_plan* plan, int32_t op, double* out_host, void* stream);
+/* Replace the FP64 weights of one operator (same layout) and re-pack them;
+ * lets the step be checked with weights computed elsewhere. */
+int rbffd_set_weights(rbffd_plan* plan, int32_t op, const double* in_host, void* stream);
+
+/* Gather / scatter a per-node array between original and internal order.
+ * to_internal = 1: out[p] = in[perm[p]]; 0: out[perm[p]] = in[p].
+ * Each node owns elem_bytes contiguous bytes (a multiple of 2). */
+int rbffd_permute(const rbffd_plan* plan, int32_t set, int32_t to_internal, int64_t elem_bytes,
+                  const void* in, void* out, void* stream);
+
+/* ---- the hot path ---------------------------------------------------------
+ * rbffd_step: nsteps full leapfrog steps (H update, then E update; eq. 19)
+ * with no sources or diagnostics.  Flips f->cur once per step. */
+int rbffd_step(const rbffd_plan* plan, rbffd_fields* f, int32_t nsteps, void* stream);
+/* rbffd_half: one half update without flipping f->cur: which = 0 writes
+ * H[1-cur] from (E[cur], H[cur]) (the H lines of eq. 19); which = 1 writes
+ * E[1-cur] from (E[cur], H[1-cur]) (the E line).  rbffd_step is the pair
+ * followed by the flip; this call exists for per-kernel timing. */
+int rbffd_half(const rbffd_plan* plan, const rbffd_fields* f, int32_t which, void* stream);
+/* rbffd_run: the forward workload with sources, receivers, energy,
+ * checkpoints, optional HIP-graph replay.  workspace: workspace_bytes. */
+int rbffd_run(const rbffd_plan* plan, rbffd_fields* f, const rbffd_run_args* args,
+              void* workspace, void* stream);
+/* rbffd_adjoint: gradients of J(traces) (see rbffd_adjoint_args). */
+int rbffd_adjoint(const rbffd_plan* plan, const rbffd_fields* f, const rbffd_adjoint_args* args,
+                  void* stream);
+
+/* ---- FP64 reductions (eq. 20, eq. 23) -------------------------------------
+ * rbffd_energy: out[0] = h^d sum |E|^2 + eta0^2 h_H^d sum |(H_a + H_b)/2|^2
+ * for the E buffer E and H buffers Ha, Hb (device double out; workspace as
+ * for rbffd_run).
+ * rbffd_compare: per component c of a field buffer (which = 0 E, 1 H) in the
+ * plan's field layout against ref [N][ncomp] doubles (internal order):
+ * out[3c + 0] = sum (f - r)^2, out[3c + 1] = sum r^2, out[3c + 2] = max |f - r|. */
+int rbffd_energy(const rbffd_plan* plan, const void* E, const void* Ha, const void* Hb,
+                 double* out, void* workspace, void* stream);
+int rbffd_compare(const rbffd_plan* plan, int32_t which, const void* field, const double* ref,
+                  double* out, void* workspace, void* stream);
+
+/* ---- launch tuning ---------------------------------------------------------
+ * Times the step kernels' launch variants on the current device with the
+ * given fields (their contents are overwritten) and keeps the fastest in the
+ * plan; reps = timed repetitions per variant.  Optional: plans start with a
+ * default that is valid everywhere. */
+int rbffd_autotune(rbffd_plan* plan, rbffd_fields* f, int32_t reps, void* stream);
+/* Active launch variant of the step kernels (for reports). */
+int rbffd_get_variant(const rbffd_plan* plan, int32_t* out_variant);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBFFD_H */

@@ -4,10 +4,12 @@ Neither is part of the paper's method (the paper leaves node order to its node
 generator); both only relabel nodes.  They are defined here bit for bit so that
 the GPU library can be checked against them exactly.
 
-Morton: per axis k, q_k = min(floor((x_k - lo_k) * scale_k), 2^b - 1) with
-scale_k = 2^b / (hi_k - lo_k) (one correctly rounded FP64 division each), b =
-32 bits in 2D and 21 in 3D; key bit (d*i + k) is bit i of q_k (x lowest).
-Nodes are sorted by (key, original index).
+Morton: the quantisation box is the cube [lo, lo + side)^d; per axis k,
+q_k = min(floor((x_k - lo_k) * scale), 2^b - 1) with scale = 2^b / side (one
+correctly rounded FP64 division), b = 32 bits in 2D and 21 in 3D; key bit
+(d*i + k) is bit i of q_k (x lowest).  Nodes are sorted by (key, original
+index).  ``morton_box`` gives the cube of a bounding box: side = the largest
+extent.
 
 RCM: graph = symmetrised stencil graph without self loops.  Start at the
 unvisited node with the smallest (degree, original index); breadth-first,
@@ -21,20 +23,20 @@ def morton_bits(d):
     return 32 if d == 2 else 21
 
 
-def morton_scale(lo, hi, d):
-    b = morton_bits(d)
-    return [float(2.0 ** b) / (float(hi[k]) - float(lo[k])) for k in range(d)]
+def morton_box(lo, hi):
+    """(lo, side) of the quantisation cube of the bounding box [lo, hi]."""
+    return tuple(float(v) for v in lo), max(float(hi[k]) - float(lo[k]) for k in range(len(lo)))
 
 
-def morton_keys(xyz, lo, hi):
+def morton_keys(xyz, lo, side):
     """uint64 Morton keys of the nodes (see module docstring)."""
     N, d = xyz.shape
     b = morton_bits(d)
-    scale = morton_scale(lo, hi, d)
+    scale = float(2.0 ** b) / float(side)
     top = np.uint64((1 << b) - 1)
     key = np.zeros(N, dtype=np.uint64)
     for k in range(d):
-        v = (xyz[:, k] - float(lo[k])) * scale[k]
+        v = (xyz[:, k] - float(lo[k])) * scale
         q = np.floor(v)
         q = np.where(q < 0, 0.0, q)
         q = np.minimum(q.astype(np.uint64), top)
@@ -44,9 +46,9 @@ def morton_keys(xyz, lo, hi):
     return key
 
 
-def morton_order(xyz, lo, hi):
+def morton_order(xyz, lo, side):
     """perm[p] = original index of the node at internal position p."""
-    key = morton_keys(xyz, lo, hi)
+    key = morton_keys(xyz, lo, side)
     return np.argsort(key, kind="stable").astype(np.int64)
 
 

@@ -1,0 +1,109 @@
+// Field storage helpers: FP64, FP32 and BF16 storage with FP64/FP32 arithmetic.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+struct bf16s {
+    uint16_t b;
+};
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+// round to nearest even
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <typename TS> struct Store;
+
+template <> struct Store<double> {
+    using C = double;
+    __device__ __forceinline__ static double ld1(const double* p, int64_t i) { return p[i]; }
+    __device__ __forceinline__ static void st1(double* p, int64_t i, double v) { p[i] = v; }
+    __device__ __forceinline__ static void ld2(const double* p, int64_t i, double& x, double& y) {
+        const double2 v = reinterpret_cast<const double2*>(p)[i];
+        x = v.x;
+        y = v.y;
+    }
+    __device__ __forceinline__ static void st2(double* p, int64_t i, double x, double y) {
+        reinterpret_cast<double2*>(p)[i] = make_double2(x, y);
+    }
+    __device__ __forceinline__ static void ld3(const double* p, int64_t i, double& x, double& y, double& z) {
+        const double2 a = reinterpret_cast<const double2*>(p)[2 * i];
+        const double b = p[4 * i + 2];
+        x = a.x;
+        y = a.y;
+        z = b;
+    }
+    __device__ __forceinline__ static void st3(double* p, int64_t i, double x, double y, double z) {
+        reinterpret_cast<double2*>(p)[2 * i] = make_double2(x, y);
+        reinterpret_cast<double2*>(p)[2 * i + 1] = make_double2(z, 0.0);
+    }
+};
+
+template <> struct Store<float> {
+    using C = float;
+    __device__ __forceinline__ static float ld1(const float* p, int64_t i) { return p[i]; }
+    __device__ __forceinline__ static void st1(float* p, int64_t i, float v) { p[i] = v; }
+    __device__ __forceinline__ static void ld2(const float* p, int64_t i, float& x, float& y) {
+        const float2 v = reinterpret_cast<const float2*>(p)[i];
+        x = v.x;
+        y = v.y;
+    }
+    __device__ __forceinline__ static void st2(float* p, int64_t i, float x, float y) {
+        reinterpret_cast<float2*>(p)[i] = make_float2(x, y);
+    }
+    __device__ __forceinline__ static void ld3(const float* p, int64_t i, float& x, float& y, float& z) {
+        const float4 v = reinterpret_cast<const float4*>(p)[i];
+        x = v.x;
+        y = v.y;
+        z = v.z;
+    }
+    __device__ __forceinline__ static void st3(float* p, int64_t i, float x, float y, float z) {
+        reinterpret_cast<float4*>(p)[i] = make_float4(x, y, z, 0.0f);
+    }
+};
+
+template <> struct Store<bf16s> {
+    using C = float;
+    __device__ __forceinline__ static float ld1(const bf16s* p, int64_t i) { return bf2f(p[i].b); }
+    __device__ __forceinline__ static void st1(bf16s* p, int64_t i, float v) { p[i].b = f2bf(v); }
+    __device__ __forceinline__ static void ld2(const bf16s* p, int64_t i, float& x, float& y) {
+        const uint32_t v = reinterpret_cast<const uint32_t*>(p)[i];
+        x = bf2f((uint16_t)(v & 0xFFFFu));
+        y = bf2f((uint16_t)(v >> 16));
+    }
+    __device__ __forceinline__ static void st2(bf16s* p, int64_t i, float x, float y) {
+        reinterpret_cast<uint32_t*>(p)[i] = (uint32_t)f2bf(x) | ((uint32_t)f2bf(y) << 16);
+    }
+    __device__ __forceinline__ static void ld3(const bf16s* p, int64_t i, float& x, float& y, float& z) {
+        const uint2 v = reinterpret_cast<const uint2*>(p)[i];
+        x = bf2f((uint16_t)(v.x & 0xFFFFu));
+        y = bf2f((uint16_t)(v.x >> 16));
+        z = bf2f((uint16_t)(v.y & 0xFFFFu));
+    }
+    __device__ __forceinline__ static void st3(bf16s* p, int64_t i, float x, float y, float z) {
+        reinterpret_cast<uint2*>(p)[i] = make_uint2((uint32_t)f2bf(x) | ((uint32_t)f2bf(y) << 16), (uint32_t)f2bf(z));
+    }
+};
+
+// four consecutive packed weights
+__device__ __forceinline__ void ldw4(const float* p, float (&w)[4]) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    w[0] = v.x;
+    w[1] = v.y;
+    w[2] = v.z;
+    w[3] = v.w;
+}
+__device__ __forceinline__ void ldw4(const double* p, double (&w)[4]) {
+    const double2 a = reinterpret_cast<const double2*>(p)[0];
+    const double2 b = reinterpret_cast<const double2*>(p)[1];
+    w[0] = a.x;
+    w[1] = a.y;
+    w[2] = b.x;
+    w[3] = b.y;
+}
+__device__ __forceinline__ int idx4(const int4& j, int u) {
+    return u == 0 ? j.x : (u == 1 ? j.y : (u == 2 ? j.z : j.w));
+}

@@ -1,0 +1,1134 @@
+// Set-up on the GPU: node ordering, exact kNN stencils, FP64 local weight
+// systems, packing for the step kernels, transposed operators for the adjoint.
+//
+// Reference: Kolar-Pozun & Kosec (arXiv 2508.18205), Section 4 (eq. 8-15:
+// stencils of the n nearest nodes, PHS + monomial interpolation systems,
+// RBF-FD and RBF-VFD right-hand sides) and Section 5.1 (hyperviscosity by
+// RBF-FD of Delta^alpha with phi = r^(2 alpha + 1), m = 2 alpha).  The paper
+// computes the weights once before time stepping; so does this file.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+#include <hipcub/hipcub.hpp>
+
+#include "common.h"
+
+namespace {
+
+constexpr int MORTON_BITS_2D = 32;
+constexpr int MORTON_BITS_3D = 21;
+
+// ---------------------------------------------------------------------------
+// Morton keys.  q_k = min(floor((x_k - lo_k) * scale), 2^b - 1), scale =
+// 2^b / side computed once on the host (one correctly rounded division); key
+// bit d*i + k = bit i of q_k.  Subtraction and multiplication are separate
+// correctly rounded operations (no contraction possible), so keys are
+// reproducible bit for bit.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t quantise(double x, double lo, double scale, int bits) {
+    double q = floor((x - lo) * scale);
+    if (q < 0.0) q = 0.0;
+    uint64_t qi = (uint64_t)q;
+    const uint64_t top = (1ull << bits) - 1ull;
+    return qi > top ? top : qi;
+}
+
+__device__ __forceinline__ uint64_t interleave(const uint64_t* q, int d, int bits) {
+    uint64_t key = 0;
+    for (int i = 0; i < bits; ++i)
+        for (int k = 0; k < d; ++k) key |= ((q[k] >> i) & 1ull) << (d * i + k);
+    return key;
+}
+
+struct MortonArgs {
+    const double* xyz;
+    int64_t N;
+    int d, bits;
+    double lo[3];
+    double scale;
+    uint64_t* keys;
+    int32_t* vals;
+};
+
+__global__ void k_morton(MortonArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    uint64_t q[3] = {0, 0, 0};
+    for (int k = 0; k < a.d; ++k) q[k] = quantise(a.xyz[i * a.d + k], a.lo[k], a.scale, a.bits);
+    a.keys[i] = interleave(q, a.d, a.bits);
+    a.vals[i] = (int32_t)i;
+}
+
+// sorted coordinates and cell ranges of the search structure
+__global__ void k_gather_sorted(const double* xyz, const int32_t* sperm, int64_t N, int d, double* sxyz) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t o = sperm[i];
+    for (int k = 0; k < d; ++k) sxyz[i * d + k] = xyz[(int64_t)o * d + k];
+}
+
+__global__ void k_cell_ranges(const uint64_t* skeys, int64_t N, int shift, int32_t* cstart, int32_t* cend) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint64_t c = skeys[i] >> shift;
+    if (i == 0 || (skeys[i - 1] >> shift) != c) cstart[c] = (int32_t)i;
+    if (i == N - 1 || (skeys[i + 1] >> shift) != c) cend[c] = (int32_t)(i + 1);
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_iota(int32_t* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// Exact k nearest neighbours.  Key of candidate j for centre c: (d2, orig_j)
+// with d2 = (dx*dx) + (dy*dy) [+ (dz*dz)], every product and sum rounded
+// separately (contraction disabled below), so the order equals the oracle's.
+// ---------------------------------------------------------------------------
+struct KnnArgs {
+    const double* cxyz;     // centres in iteration order [Nc][d]
+    const int32_t* crow;    // output row of each centre
+    int64_t Nc;
+    const double* sxyz;     // sources sorted by Morton key [Ns][d]
+    const int32_t* sorig;   // original id of each sorted source
+    int64_t Ns;
+    const int32_t* cstart;  // cell ranges (cells mode)
+    const int32_t* cend;
+    int d, k, L, bits;
+    double lo[3];
+    double scale, side;
+    double period[3];       // > 0: periodic axis length (brute-force mode)
+    int periodic;
+    int32_t* out;           // [rows][k] original source ids
+};
+
+__device__ __forceinline__ double sq_dist(const double* a, const double* b, int d, const double* per, int periodic) {
+#pragma clang fp contract(off)
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double dk = b[k] - a[k];
+        if (periodic) {
+            const double L = per[k];
+            if (dk > 0.5 * L) dk = dk - L;
+            if (dk < -0.5 * L) dk = dk + L;
+        }
+        const double s = dk * dk;
+        acc = (k == 0) ? s : acc + s;
+    }
+    return acc;
+}
+
+template <int KMAX>
+struct TopK {
+    double d2[KMAX];
+    int32_t id[KMAX];
+    int cnt = 0;
+    __device__ __forceinline__ void push(double dd, int32_t o, int k) {
+        if (cnt == k) {
+            const double wd = d2[k - 1];
+            if (!(dd < wd || (dd == wd && o < id[k - 1]))) return;
+        } else {
+            ++cnt;
+        }
+        int pos = cnt - 1;
+        while (pos > 0 && (dd < d2[pos - 1] || (dd == d2[pos - 1] && o < id[pos - 1]))) {
+            d2[pos] = d2[pos - 1];
+            id[pos] = id[pos - 1];
+            --pos;
+        }
+        d2[pos] = dd;
+        id[pos] = o;
+    }
+};
+
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.Nc) return;
+    double c[3] = {0, 0, 0};
+    for (int k = 0; k < a.d; ++k) c[k] = a.cxyz[t * a.d + k];
+    TopK<KMAX> tk;
+    if (a.periodic) {
+        for (int64_t j = 0; j < a.Ns; ++j) tk.push(sq_dist(c, a.sxyz + j * a.d, a.d, a.period, 1), a.sorig[j], a.k);
+    } else {
+        const int G = 1 << a.L;
+        const double cs = a.side / G;
+        int cc[3] = {0, 0, 0};
+        for (int k = 0; k < a.d; ++k) cc[k] = (int)(quantise(c[k], a.lo[k], a.scale, a.bits) >> (a.bits - a.L));
+        for (int r = 0;; ++r) {
+            const int z0 = a.d == 3 ? -r : 0, z1 = a.d == 3 ? r : 0;
+            for (int dz = z0; dz <= z1; ++dz)
+                for (int dy = -r; dy <= r; ++dy)
+                    for (int dx = -r; dx <= r; ++dx) {
+                        const int m = max(abs(dx), max(abs(dy), abs(dz)));
+                        if (m != r) continue;
+                        const int x = cc[0] + dx, y = cc[1] + dy, z = cc[2] + dz;
+                        if (x < 0 || x >= G || y < 0 || y >= G || (a.d == 3 && (z < 0 || z >= G))) continue;
+                        uint64_t q[3] = {(uint64_t)x, (uint64_t)y, (uint64_t)z};
+                        const uint64_t cid = interleave(q, a.d, a.L);
+                        const int32_t e = a.cend[cid];
+                        for (int32_t j = a.cstart[cid]; j < e; ++j)
+                            tk.push(sq_dist(c, a.sxyz + (int64_t)j * a.d, a.d, a.period, 0), a.sorig[j], a.k);
+                    }
+            // every node outside the scanned box is at least R away
+            bool whole = true;
+            double R = 1e300;
+            for (int k = 0; k < a.d; ++k) {
+                if (cc[k] - r > 0) {
+                    whole = false;
+                    R = fmin(R, c[k] - (a.lo[k] + (cc[k] - r) * cs));
+                }
+                if (cc[k] + r < G - 1) {
+                    whole = false;
+                    R = fmin(R, (a.lo[k] + (cc[k] + r + 1) * cs) - c[k]);
+                }
+            }
+            if (whole) break;
+            R -= 1e-9 * cs;
+            if (tk.cnt >= a.k && R > 0.0 && tk.d2[a.k - 1] < R * R) break;
+        }
+    }
+    const int64_t row = a.crow[t];
+    for (int s = 0; s < a.k; ++s) a.out[row * a.k + s] = s < tk.cnt ? tk.id[s] : -1;
+}
+
+// relabel stencils of the target set into internal order
+__global__ void k_relabel(const int32_t* knn_orig, int k, const int32_t* tperm, const int32_t* sinv, int64_t Nt,
+                          int32_t* st, int width) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= Nt) return;
+    const int64_t o = tperm[p];
+    for (int s = 0; s < width; ++s) st[p * width + s] = sinv[knn_orig[o * k + s]];
+}
+
+__global__ void k_internal_nodes(const double* xyz_in, const uint8_t* flags_in, const int32_t* perm, int64_t N, int d,
+                                 double* xyz, uint8_t* emask, int periodic) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int64_t o = perm[p];
+    for (int k = 0; k < d; ++k) xyz[p * d + k] = xyz_in[o * d + k];
+    if (!emask) return;
+    const uint8_t f = periodic ? 0 : flags_in[o];
+    uint8_t keep;
+    if (d == 2) {
+        keep = f == 0 ? 1 : 0;              // Ez is tangential to every wall
+    } else {
+        keep = 7;
+        for (int k = 0; k < 3; ++k)
+            if (f & (3u << (2 * k))) keep &= (uint8_t)(1u << k);   // only the normal component survives
+    }
+    emask[p] = keep;
+}
+
+__global__ void k_inverse(const int32_t* perm, int64_t N, int32_t* inv) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) inv[perm[p]] = (int32_t)p;
+}
+
+// ---------------------------------------------------------------------------
+// Local weight systems (eq. 9 with eq. 13 / eq. 15 right-hand sides; HV by
+// RBF-FD of Delta^alpha).  One workgroup per centre, the augmented matrix
+// [A~ | B] lives in LDS; Gaussian elimination with partial pivoting (largest
+// |pivot|, lowest row on ties) and back substitution in FP64.
+// ---------------------------------------------------------------------------
+enum { W_FD = 0, W_VFD = 1, W_HV = 2 };
+
+struct WArgs {
+    const double* txyz;   // target centres (internal order) [Nt][d]
+    const double* sxyz;   // source nodes (internal order) [Ns][d]
+    const int32_t* st;    // stencil rows (internal labels of the source set)
+    int st_stride;
+    int n;                // stencil entries used
+    int M;                // monomials
+    int d;
+    int kind;
+    int phs_k;
+    int nrhs;
+    int upow;             // unscaling power l
+    int periodic;
+    double period[3];
+    double vdelta;        // RBF-VFD virtual spacing (unscaled)
+    double hv_C;          // Delta^alpha r^(2a+1) = hv_C r
+    double hv_poly[RBFFD_MAX_MONO];
+    int8_t ex[RBFFD_MAX_MONO][3];
+    double* out;          // [Nt][nrhs][n]
+    int64_t Nt;
+    int32_t* status;      // status[0] = first singular centre (atomicMin), status[1] = self-first violations
+    int check_self;
+};
+
+__device__ __forceinline__ double ipow(double x, int e) {
+    double r = 1.0;
+    for (int i = 0; i < e; ++i) r *= x;
+    return r;
+}
+
+__device__ __forceinline__ double phs(double r, int k) {
+    // r^k for odd k >= 3
+    double r2 = r * r;
+    double v = r;
+    for (int i = 0; i < (k - 1) / 2; ++i) v *= r2;
+    return v;
+}
+
+__device__ __forceinline__ double mono(const double* x, const int8_t* e, int d) {
+    double v = 1.0;
+    for (int k = 0; k < d; ++k) v *= ipow(x[k], e[k]);
+    return v;
+}
+
+__device__ __forceinline__ double dmono_at0(const int8_t* e, int d, int axis) {
+    int deg = 0;
+    for (int k = 0; k < d; ++k) deg += e[k];
+    return (deg == 1 && e[axis] == 1) ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_weights(WArgs a) {
+    extern __shared__ double lds[];
+    const int64_t c = blockIdx.x;
+    if (c >= a.Nt) return;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int n = a.n, M = a.M, R = n + M, d = a.d;
+    const int lda = R + a.nrhs;
+    double* Am = lds;                        // [R][lda]
+    double* xi = Am + R * lda;               // [n][3]
+    double* piv = xi + n * 3;                // [R] multipliers
+    __shared__ double s_scale;
+    __shared__ int s_p;
+    __shared__ int s_bad;
+
+    // 1. offsets from the centre and the stencil radius
+    const double* xc = a.txyz + c * d;
+    const int32_t* row = a.st + c * a.st_stride;
+    for (int j = tid; j < n; j += nt) {
+        const double* xj = a.sxyz + (int64_t)row[j] * d;
+        for (int k = 0; k < 3; ++k) xi[j * 3 + k] = 0.0;
+        for (int k = 0; k < d; ++k) {
+            double dk = xj[k] - xc[k];
+            if (a.periodic) {
+                const double L = a.period[k];
+                if (dk > 0.5 * L) dk -= L;
+                if (dk < -0.5 * L) dk += L;
+            }
+            xi[j * 3 + k] = dk;
+        }
+    }
+    if (tid == 0) {
+        s_bad = 0;
+        if (a.check_self && row[0] != (int32_t)c) atomicAdd(&a.status[1], 1);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        double mx = 0.0;
+        for (int j = tid; j < n; j += 64) {
+            double r2 = 0.0;
+            for (int k = 0; k < d; ++k) r2 += xi[j * 3 + k] * xi[j * 3 + k];
+            mx = fmax(mx, sqrt(r2));
+        }
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+        if (tid == 0) s_scale = mx;
+    }
+    __syncthreads();
+    const double sc = s_scale;
+    for (int j = tid; j < n * 3; j += nt) xi[j] = xi[j] / sc;
+    __syncthreads();
+
+    // 2. assemble [A~ | B]
+    for (int e = tid; e < R * lda; e += nt) {
+        const int i = e / lda, j = e % lda;
+        double v = 0.0;
+        if (j < R) {
+            if (i < n && j < n) {
+                double r2 = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    const double t = xi[i * 3 + k] - xi[j * 3 + k];
+                    r2 += t * t;
+                }
+                v = phs(sqrt(r2), a.phs_k);
+            } else if (i < n && j >= n) {
+                v = mono(xi + i * 3, a.ex[j - n], d);
+            } else if (i >= n && j < n) {
+                v = mono(xi + j * 3, a.ex[i - n], d);
+            }
+        } else {
+            const int col = j - R;   // right-hand side index (axis for derivatives)
+            if (a.kind == W_FD) {
+                if (i < n) {
+                    double r2 = 0.0;
+                    for (int k = 0; k < d; ++k) r2 += xi[i * 3 + k] * xi[i * 3 + k];
+                    const double r = sqrt(r2);
+                    // d/dx_col |x - xi_i|^k at x = 0 = -k r^(k-2) xi_{i,col}
+                    v = -(double)a.phs_k * phs(r, a.phs_k - 2) * xi[i * 3 + col];
+                } else {
+                    v = dmono_at0(a.ex[i - n], d, col);
+                }
+            } else if (a.kind == W_VFD) {
+                // central virtual difference: (-1/2 f(-delta e) + 1/2 f(+delta e)) / delta
+                const double dl = a.vdelta / sc;
+                double xm[3] = {0, 0, 0}, xp[3] = {0, 0, 0};
+                xm[col] = -dl;
+                xp[col] = dl;
+                double fm, fp;
+                if (i < n) {
+                    double r2m = 0.0, r2p = 0.0;
+                    for (int k = 0; k < d; ++k) {
+                        const double tm = xm[k] - xi[i * 3 + k], tp = xp[k] - xi[i * 3 + k];
+                        r2m += tm * tm;
+                        r2p += tp * tp;
+                    }
+                    fm = phs(sqrt(r2m), a.phs_k);
+                    fp = phs(sqrt(r2p), a.phs_k);
+                } else {
+                    fm = mono(xm, a.ex[i - n], d);
+                    fp = mono(xp, a.ex[i - n], d);
+                }
+                v = (-0.5 * fm + 0.5 * fp) / dl;
+            } else {
+                if (i < n) {
+                    double r2 = 0.0;
+                    for (int k = 0; k < d; ++k) r2 += xi[i * 3 + k] * xi[i * 3 + k];
+                    v = a.hv_C * sqrt(r2);
+                } else {
+                    v = a.hv_poly[i - n];
+                }
+            }
+        }
+        Am[i * lda + j] = v;
+    }
+    __syncthreads();
+
+    // 3. forward elimination with partial pivoting
+    for (int k = 0; k < R; ++k) {
+        if (tid < 64) {
+            double best = -1.0;
+            int bi = R;
+            for (int i = k + tid; i < R; i += 64) {
+                const double v = fabs(Am[i * lda + k]);
+                if (v > best) { best = v; bi = i; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_down(best, off, 64);
+                const int oi = __shfl_down(bi, off, 64);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (tid == 0) {
+                s_p = bi;
+                if (!(best > 0.0)) s_bad = 1;
+            }
+        }
+        __syncthreads();
+        if (s_bad) break;
+        const int p = s_p;
+        if (p != k)
+            for (int j = k + tid; j < lda; j += nt) {
+                const double t = Am[k * lda + j];
+                Am[k * lda + j] = Am[p * lda + j];
+                Am[p * lda + j] = t;
+            }
+        __syncthreads();
+        const double pk = Am[k * lda + k];
+        for (int i = k + 1 + tid; i < R; i += nt) piv[i] = Am[i * lda + k] / pk;
+        __syncthreads();
+        const int rows = R - k - 1, cols = lda - k - 1;
+        for (int e = tid; e < rows * cols; e += nt) {
+            const int i = k + 1 + e / cols, j = k + 1 + e % cols;
+            Am[i * lda + j] -= piv[i] * Am[k * lda + j];
+        }
+        __syncthreads();
+    }
+    if (s_bad) {
+        if (tid == 0) atomicMin(&a.status[0], (int32_t)c);
+        for (int e = tid; e < a.nrhs * n; e += nt) a.out[c * a.nrhs * n + e] = 0.0;
+        return;
+    }
+    // 4. back substitution, column by column of the unknowns
+    for (int i = R - 1; i >= 0; --i) {
+        const double di = Am[i * lda + i];
+        for (int q = tid; q < a.nrhs; q += nt) Am[i * lda + R + q] /= di;
+        __syncthreads();
+        for (int e = tid; e < i * a.nrhs; e += nt) {
+            const int r = e / a.nrhs, q = e % a.nrhs;
+            Am[r * lda + R + q] -= Am[r * lda + i] * Am[i * lda + R + q];
+        }
+        __syncthreads();
+    }
+    // 5. unscale and store the first n entries
+    const double us = ipow(sc, a.upow);
+    for (int e = tid; e < a.nrhs * n; e += nt) {
+        const int q = e / n, j = e % n;
+        a.out[c * a.nrhs * n + e] = Am[j * lda + R + q] / us;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Packing for the step kernels
+// ---------------------------------------------------------------------------
+template <typename TW>
+__global__ void k_pack_union(const int32_t* st, const double* wc, const double* wh, int64_t N, int ns, int n, int nh,
+                             int d, int C4, int V4, int S4, int64_t tiles, int4* pidx, TW* pwc, TW* pwh) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (tile, lane)
+    if (g >= tiles * RBFFD_TILE) return;
+    const int64_t tile = g / RBFFD_TILE;
+    const int lane = (int)(g % RBFFD_TILE);
+    const int64_t i = g;
+    const bool real = i < N;
+    const int64_t ic = real ? i : N - 1;
+    for (int q = 0; q < S4; ++q) {
+        int v[4];
+        for (int u = 0; u < 4; ++u) {
+            const int s = 1 + 4 * q + u;
+            v[u] = (real && s < ns) ? st[ic * ns + s] : (int)ic;
+        }
+        pidx[(tile * S4 + q) * RBFFD_TILE + lane] = make_int4(v[0], v[1], v[2], v[3]);
+    }
+    for (int q = 0; q < C4; ++q)
+        for (int ax = 0; ax < d; ++ax)
+            for (int u = 0; u < 4; ++u) {
+                const int s = 1 + 4 * q + u;
+                const double w = (real && s < n) ? wc[(ic * d + ax) * n + s] : 0.0;
+                pwc[(((tile * C4 + q) * d + ax) * RBFFD_TILE + lane) * 4 + u] = (TW)w;
+            }
+    for (int q = 0; q < V4; ++q)
+        for (int u = 0; u < 4; ++u) {
+            const int s = 1 + 4 * q + u;
+            const double w = (real && s < nh) ? wh[ic * nh + s] : 0.0;
+            pwh[((tile * V4 + q) * RBFFD_TILE + lane) * 4 + u] = (TW)w;
+        }
+}
+
+template <typename TW>
+__global__ void k_pack_cross(const int32_t* stc, const int32_t* sth, const double* wc, const double* wh, int64_t N,
+                             int n, int nh, int d, int C4, int V4, int64_t tiles, int4* pidx, int4* pidx_h,
+                             int32_t* pref, TW* pwc, TW* pwh) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= tiles * RBFFD_TILE) return;
+    const int64_t tile = g / RBFFD_TILE;
+    const int lane = (int)(g % RBFFD_TILE);
+    const bool real = g < N;
+    const int64_t ic = real ? g : N - 1;
+    const int ref = stc[ic * n];
+    if (real) pref[g] = ref;
+    for (int q = 0; q < C4; ++q) {
+        int v[4];
+        for (int u = 0; u < 4; ++u) {
+            const int s = 1 + 4 * q + u;
+            v[u] = (real && s < n) ? stc[ic * n + s] : ref;
+        }
+        pidx[(tile * C4 + q) * RBFFD_TILE + lane] = make_int4(v[0], v[1], v[2], v[3]);
+        for (int ax = 0; ax < d; ++ax)
+            for (int u = 0; u < 4; ++u) {
+                const int s = 1 + 4 * q + u;
+                const double w = (real && s < n) ? wc[(ic * d + ax) * n + s] : 0.0;
+                pwc[(((tile * C4 + q) * d + ax) * RBFFD_TILE + lane) * 4 + u] = (TW)w;
+            }
+    }
+    for (int q = 0; q < V4; ++q) {
+        int v[4];
+        for (int u = 0; u < 4; ++u) {
+            const int s = 1 + 4 * q + u;
+            v[u] = (real && s < nh) ? sth[ic * nh + s] : (int)ic;
+            const double w = (real && s < nh) ? wh[ic * nh + s] : 0.0;
+            pwh[((tile * V4 + q) * RBFFD_TILE + lane) * 4 + u] = (TW)w;
+        }
+        pidx_h[(tile * V4 + q) * RBFFD_TILE + lane] = make_int4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+__global__ void k_pack_batched(const int32_t* st, const double* wc, const double* wh, int64_t N, int ns, int n, int nh,
+                               int d, int C4, int V4, int S4, int32_t* bidx, float* bwc, float* bwh) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int s4 = 0; s4 < S4 * 4; ++s4) {
+        const int s = 1 + s4;
+        bidx[i * S4 * 4 + s4] = s < ns ? st[i * ns + s] : (int)i;
+    }
+    for (int ax = 0; ax < d; ++ax)
+        for (int s4 = 0; s4 < C4 * 4; ++s4) {
+            const int s = 1 + s4;
+            bwc[(i * d + ax) * C4 * 4 + s4] = s < n ? (float)wc[(i * d + ax) * n + s] : 0.0f;
+        }
+    for (int s4 = 0; s4 < V4 * 4; ++s4) {
+        const int s = 1 + s4;
+        bwh[i * V4 * 4 + s4] = s < nh ? (float)wh[i * nh + s] : 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Transposed operator (adjoint): entries (j <- i, slot s) sorted by (j, i, s)
+// ---------------------------------------------------------------------------
+__global__ void k_tkeys(const int32_t* st, int64_t N, int ns, uint64_t* keys) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= N * ns) return;
+    const int64_t i = e / ns;
+    const int s = (int)(e % ns);
+    const uint64_t j = (uint64_t)st[e];
+    keys[e] = j * (uint64_t)(N * ns) + (uint64_t)(i * ns + s);
+}
+
+__global__ void k_tdeg(const uint64_t* skeys, int64_t E, int64_t Nns, int32_t* rstart, int32_t* rend) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const int64_t j = (int64_t)(skeys[e] / (uint64_t)Nns);
+    if (e == 0 || (int64_t)(skeys[e - 1] / (uint64_t)Nns) != j) rstart[j] = (int32_t)e;
+    if (e == E - 1 || (int64_t)(skeys[e + 1] / (uint64_t)Nns) != j) rend[j] = (int32_t)(e + 1);
+}
+
+__global__ void k_twidth(const int32_t* rstart, const int32_t* rend, int64_t N, int64_t tiles, int32_t* width) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tiles) return;
+    int w = 0;
+    for (int l = 0; l < RBFFD_TILE; ++l) {
+        const int64_t j = t * RBFFD_TILE + l;
+        if (j < N) w = max(w, rend[j] - rstart[j]);
+    }
+    width[t] = w;
+}
+
+template <typename TW>
+__global__ void k_tfill(const uint64_t* skeys, const int32_t* rstart, const int32_t* rend, const int64_t* toff,
+                        const int32_t* width, const double* wc, const double* wh, int64_t N, int ns, int n, int nh,
+                        int64_t tiles, int32_t* tsrc, TW* tw) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= tiles * RBFFD_TILE) return;
+    const int64_t t = g / RBFFD_TILE;
+    const int l = (int)(g % RBFFD_TILE);
+    const int64_t j = g;
+    const int w = width[t];
+    const int deg = j < N ? rend[j] - rstart[j] : 0;
+    const int64_t jc = j < N ? j : N - 1;
+    for (int q = 0; q < w; ++q) {
+        const int64_t e = toff[t] + (int64_t)q * RBFFD_TILE + l;
+        if (q < deg) {
+            const uint64_t key = skeys[rstart[j] + q];
+            const int64_t rem = (int64_t)(key % (uint64_t)(N * ns));
+            const int64_t i = rem / ns;
+            const int s = (int)(rem % ns);
+            tsrc[e] = (int32_t)i;
+            tw[e * 4 + 0] = (TW)(s < n ? wc[(i * 2 + 0) * n + s] : 0.0);
+            tw[e * 4 + 1] = (TW)(s < n ? wc[(i * 2 + 1) * n + s] : 0.0);
+            tw[e * 4 + 2] = (TW)(s < nh ? wh[i * nh + s] : 0.0);
+            tw[e * 4 + 3] = (TW)0.0;
+        } else {
+            tsrc[e] = (int32_t)jc;
+            for (int c = 0; c < 4; ++c) tw[e * 4 + c] = (TW)0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// workspace bump allocator
+// ---------------------------------------------------------------------------
+struct WS {
+    char* base;
+    int64_t off = 0;
+    template <typename T>
+    T* take(int64_t count) {
+        off = align_up(off, 256);
+        T* r = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * (int64_t)sizeof(T);
+        return r;
+    }
+};
+
+inline int blocks(int64_t n, int b = 256) { return (int)cdiv(n, b); }
+
+int cell_level(int64_t N, int d, int width) {
+    const double target = std::max(8.0, width * 0.5);
+    const double cells = std::max(1.0, (double)N / target);
+    int L = (int)std::lround(std::log2(cells) / d);
+    const int maxL = d == 2 ? 11 : 7;
+    return std::max(1, std::min(L, maxL));
+}
+
+// Temporary storage of the radix sorts.  The query needs no device memory;
+// should it fail (no device visible) a generous bound is used instead, which
+// only matters for sizes reported before any GPU work.
+size_t sort_temp_bytes(int64_t N) {
+    size_t t = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, t, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
+                                           (int32_t*)nullptr, (int)N, 0, 64) != hipSuccess)
+        t = (size_t)N * 24 + (1u << 22);
+    return t;
+}
+
+size_t key_sort_temp_bytes(int64_t E) {
+    size_t t = 0;
+    if (hipcub::DeviceRadixSort::SortKeys(nullptr, t, (uint64_t*)nullptr, (uint64_t*)nullptr, (int)E, 0, 64) !=
+        hipSuccess)
+        t = (size_t)E * 16 + (1u << 22);
+    return t;
+}
+
+// Search structure of one node set inside the workspace
+struct Search {
+    uint64_t* keys_in;
+    uint64_t* keys;
+    int32_t* vals_in;
+    int32_t* sperm;     // sorted position -> original id
+    double* sxyz;       // sorted coordinates
+    int32_t* cstart;
+    int32_t* cend;
+    void* temp;
+    size_t temp_bytes;
+    int L;
+    int64_t ncells;
+};
+
+void take_search(WS& w, Search& s, int64_t N, int d, int width, bool periodic) {
+    s.keys_in = w.take<uint64_t>(N);
+    s.keys = w.take<uint64_t>(N);
+    s.vals_in = w.take<int32_t>(N);
+    s.sperm = w.take<int32_t>(N);
+    s.sxyz = w.take<double>(N * d);
+    s.L = periodic ? 1 : cell_level(N, d, width);
+    s.ncells = (int64_t)1 << (d * s.L);
+    s.cstart = w.take<int32_t>(s.ncells);
+    s.cend = w.take<int32_t>(s.ncells);
+    s.temp_bytes = sort_temp_bytes(N);
+    s.temp = w.take<char>((int64_t)s.temp_bytes);
+}
+
+int build_search(rbffd_plan* p, NodeSet& S, Search& s, hipStream_t st) {
+    const int d = p->dim;
+    const int bits = d == 2 ? MORTON_BITS_2D : MORTON_BITS_3D;
+    MortonArgs ma{};
+    ma.xyz = S.xyz_in;
+    ma.N = S.N;
+    ma.d = d;
+    ma.bits = bits;
+    for (int k = 0; k < 3; ++k) ma.lo[k] = p->mlo[k];
+    ma.scale = std::ldexp(1.0, bits) / p->mside;
+    ma.keys = s.keys_in;
+    ma.vals = s.vals_in;
+    hipLaunchKernelGGL(k_morton, dim3(blocks(S.N)), dim3(256), 0, st, ma);
+    size_t tb = s.temp_bytes;
+    HIPCHK(p, hipcub::DeviceRadixSort::SortPairs(s.temp, tb, s.keys_in, s.keys, s.vals_in, s.sperm, (int)S.N, 0,
+                                                 d * bits, st));
+    hipLaunchKernelGGL(k_gather_sorted, dim3(blocks(S.N)), dim3(256), 0, st, S.xyz_in, s.sperm, S.N, d, s.sxyz);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(s.ncells)), dim3(256), 0, st, s.cstart, s.ncells, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(s.ncells)), dim3(256), 0, st, s.cend, s.ncells, 0);
+    hipLaunchKernelGGL(k_cell_ranges, dim3(blocks(S.N)), dim3(256), 0, st, s.keys, S.N, d * (bits - s.L), s.cstart,
+                       s.cend);
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
+
+// kNN of the centres of set C (iterated in C's search order) among set S
+int run_knn(rbffd_plan* p, const Search& cs, const Search& ss, int64_t Nc, int64_t Ns, int k, int32_t* out,
+            hipStream_t st) {
+    const int d = p->dim;
+    const int bits = d == 2 ? MORTON_BITS_2D : MORTON_BITS_3D;
+    KnnArgs a{};
+    a.cxyz = cs.sxyz;
+    a.crow = cs.sperm;
+    a.Nc = Nc;
+    a.sxyz = ss.sxyz;
+    a.sorig = ss.sperm;
+    a.Ns = Ns;
+    a.cstart = ss.cstart;
+    a.cend = ss.cend;
+    a.d = d;
+    a.k = k;
+    a.L = ss.L;
+    a.bits = bits;
+    for (int q = 0; q < 3; ++q) a.lo[q] = p->mlo[q];
+    a.scale = std::ldexp(1.0, bits) / p->mside;
+    a.side = p->mside;
+    a.periodic = p->p.bc == RBFFD_BC_PERIODIC;
+    for (int q = 0; q < 3; ++q) a.period[q] = p->p.hi[q] - p->p.lo[q];
+    a.out = out;
+    const dim3 g(blocks(Nc, 64)), b(64);
+    if (k <= 32) hipLaunchKernelGGL(k_knn<32>, g, b, 0, st, a);
+    else if (k <= 64) hipLaunchKernelGGL(k_knn<64>, g, b, 0, st, a);
+    else hipLaunchKernelGGL(k_knn<128>, g, b, 0, st, a);
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
+
+// Reverse Cuthill-McKee on the host from the curl stencils (original labels):
+// start at the unvisited node of smallest (degree, id), breadth first,
+// neighbours in increasing (degree, id), every component, then reverse.
+std::vector<int32_t> rcm_host(const std::vector<int32_t>& knn, int64_t N, int width, int ncurl) {
+    std::vector<std::vector<int32_t>> nb(N);
+    for (int64_t i = 0; i < N; ++i)
+        for (int s = 0; s < ncurl; ++s) {
+            const int32_t j = knn[i * width + s];
+            if (j != i) {
+                nb[i].push_back(j);
+                nb[j].push_back((int32_t)i);
+            }
+        }
+    std::vector<int32_t> deg(N);
+    for (int64_t i = 0; i < N; ++i) {
+        std::sort(nb[i].begin(), nb[i].end());
+        nb[i].erase(std::unique(nb[i].begin(), nb[i].end()), nb[i].end());
+        deg[i] = (int32_t)nb[i].size();
+    }
+    auto less = [&](int32_t a, int32_t b) { return deg[a] < deg[b] || (deg[a] == deg[b] && a < b); };
+    std::vector<int32_t> by(N);
+    std::iota(by.begin(), by.end(), 0);
+    std::sort(by.begin(), by.end(), less);
+    std::vector<char> vis(N, 0);
+    std::vector<int32_t> order;
+    order.reserve(N);
+    std::vector<int32_t> tmp;
+    for (int32_t s0 : by) {
+        if (vis[s0]) continue;
+        vis[s0] = 1;
+        size_t head = order.size();
+        order.push_back(s0);
+        while (head < order.size()) {
+            const int32_t v = order[head++];
+            tmp.clear();
+            for (int32_t u : nb[v])
+                if (!vis[u]) tmp.push_back(u);
+            std::sort(tmp.begin(), tmp.end(), less);
+            for (int32_t u : tmp) {
+                vis[u] = 1;
+                order.push_back(u);
+            }
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+int64_t setup_ws_bytes(const rbffd_plan* p) {
+    WS w{nullptr};
+    Search a{}, b{};
+    const bool per = p->p.bc == RBFFD_BC_PERIODIC;
+    take_search(w, a, p->E.N, p->dim, p->ns, per);
+    if (!p->collocated) take_search(w, b, p->H.N, p->dim, p->ns, per);
+    // kNN outputs (original labels)
+    if (p->collocated) {
+        w.take<int32_t>(p->E.N * p->ns);
+    } else {
+        w.take<int32_t>(p->H.N * p->n);
+        w.take<int32_t>(p->H.N * std::max(p->nh, 1));
+        w.take<int32_t>(p->E.N * p->n);
+        w.take<int32_t>(p->E.N * std::max(p->nh, 1));
+    }
+    w.take<int32_t>(64);   // status
+    int64_t need = w.off;
+    if (p->p.adjoint) {
+        WS t{nullptr};
+        const int64_t E = p->E.N * p->ns;
+        t.take<uint64_t>(E);
+        t.take<uint64_t>(E);
+        t.take<int32_t>(p->E.N);
+        t.take<int32_t>(p->E.N);
+        t.take<char>((int64_t)key_sort_temp_bytes(E));
+        need = std::max(need, t.off);
+    }
+    return align_up(need, 256) + 4096;
+}
+
+static int stage_status(rbffd_plan* p, int32_t* status, hipStream_t s) {
+    int32_t h[2];
+    HIPCHK(p, hipMemcpyAsync(h, status, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(p, hipStreamSynchronize(s));
+    if (h[1] != 0)
+        return set_err(p, RBFFD_ESINGULAR, "duplicate node positions: " + std::to_string(h[1]) +
+                                               " nodes are not first in their own stencil");
+    if (h[0] != INT32_MAX)
+        return set_err(p, RBFFD_ESINGULAR, "singular local system at internal node " + std::to_string(h[0]));
+    return RBFFD_OK;
+}
+
+// Node reordering and stencils; weights; packing -- driven by rbffd_weights.
+int setup_nodes_and_stencils(rbffd_plan* p, void* wsp, hipStream_t st) {
+    WS w{(char*)wsp};
+    const bool per = p->p.bc == RBFFD_BC_PERIODIC;
+    const int d = p->dim;
+    Search se{}, sh{};
+    take_search(w, se, p->E.N, d, p->ns, per);
+    if (!p->collocated) take_search(w, sh, p->H.N, d, p->ns, per);
+    int32_t *kE = nullptr, *kHc = nullptr, *kHh = nullptr, *kEc = nullptr, *kEh = nullptr;
+    if (p->collocated) {
+        kE = w.take<int32_t>(p->E.N * p->ns);
+    } else {
+        kHc = w.take<int32_t>(p->H.N * p->n);
+        kHh = w.take<int32_t>(p->H.N * std::max(p->nh, 1));
+        kEc = w.take<int32_t>(p->E.N * p->n);
+        kEh = w.take<int32_t>(p->E.N * std::max(p->nh, 1));
+    }
+    int32_t* status = w.take<int32_t>(64);
+    // upload node data
+    HIPCHK(p, hipMemcpyAsync(p->E.xyz_in, p->E.xyz_host.data(), p->E.N * d * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(p, hipMemcpyAsync(p->E.flags_in, p->E.flags_host.data(), p->E.N, hipMemcpyHostToDevice, st));
+    int rc = build_search(p, p->E, se, st);
+    if (rc) return rc;
+    if (!p->collocated) {
+        HIPCHK(p, hipMemcpyAsync(p->H.xyz_in, p->H.xyz_host.data(), p->H.N * d * 8, hipMemcpyHostToDevice, st));
+        HIPCHK(p, hipMemcpyAsync(p->H.flags_in, p->H.flags_host.data(), p->H.N, hipMemcpyHostToDevice, st));
+        rc = build_search(p, p->H, sh, st);
+        if (rc) return rc;
+    }
+    // stencils in original labels
+    if (p->collocated) {
+        rc = run_knn(p, se, se, p->E.N, p->E.N, p->ns, kE, st);
+        if (rc) return rc;
+    } else {
+        if ((rc = run_knn(p, sh, se, p->H.N, p->E.N, p->n, kHc, st))) return rc;
+        if (p->nh > 0 && (rc = run_knn(p, sh, sh, p->H.N, p->H.N, p->nh, kHh, st))) return rc;
+        if ((rc = run_knn(p, se, sh, p->E.N, p->H.N, p->n, kEc, st))) return rc;
+        if (p->nh > 0 && (rc = run_knn(p, se, se, p->E.N, p->E.N, p->nh, kEh, st))) return rc;
+    }
+    // internal order
+    auto order_set = [&](NodeSet& S, Search& s) -> int {
+        if (p->p.reorder == RBFFD_ORDER_MORTON) {
+            HIPCHK(p, hipMemcpyAsync(S.perm, s.sperm, S.N * 4, hipMemcpyDeviceToDevice, st));
+        } else if (p->p.reorder == RBFFD_ORDER_NONE || !p->collocated) {
+            hipLaunchKernelGGL(k_iota, dim3(blocks(S.N)), dim3(256), 0, st, S.perm, S.N);
+        } else {
+            std::vector<int32_t> kh(S.N * p->ns);
+            HIPCHK(p, hipMemcpyAsync(kh.data(), kE, S.N * p->ns * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(p, hipStreamSynchronize(st));
+            std::vector<int32_t> order = rcm_host(kh, S.N, p->ns, p->n);
+            HIPCHK(p, hipMemcpyAsync(S.perm, order.data(), S.N * 4, hipMemcpyHostToDevice, st));
+            HIPCHK(p, hipStreamSynchronize(st));
+        }
+        hipLaunchKernelGGL(k_inverse, dim3(blocks(S.N)), dim3(256), 0, st, S.perm, S.N, S.inv);
+        hipLaunchKernelGGL(k_internal_nodes, dim3(blocks(S.N)), dim3(256), 0, st, S.xyz_in, S.flags_in, S.perm, S.N, d,
+                           S.xyz, S.emask, (int)per);
+        return RBFFD_OK;
+    };
+    if (p->p.reorder == RBFFD_ORDER_RCM && !p->collocated)
+        return set_err(p, RBFFD_ENOTSUP, "RCM ordering is implemented for collocated plans");
+    if ((rc = order_set(p->E, se))) return rc;
+    if (!p->collocated && (rc = order_set(p->H, sh))) return rc;
+    if (p->collocated) {
+        hipLaunchKernelGGL(k_relabel, dim3(blocks(p->E.N)), dim3(256), 0, st, kE, p->ns, p->E.perm, p->E.inv, p->E.N,
+                           p->opH.st_union, p->ns);
+    } else {
+        hipLaunchKernelGGL(k_relabel, dim3(blocks(p->H.N)), dim3(256), 0, st, kHc, p->n, p->H.perm, p->E.inv, p->H.N,
+                           p->opH.st_curl, p->n);
+        hipLaunchKernelGGL(k_relabel, dim3(blocks(p->E.N)), dim3(256), 0, st, kEc, p->n, p->E.perm, p->H.inv, p->E.N,
+                           p->opE.st_curl, p->n);
+        if (p->nh > 0) {
+            hipLaunchKernelGGL(k_relabel, dim3(blocks(p->H.N)), dim3(256), 0, st, kHh, p->nh, p->H.perm, p->H.inv,
+                               p->H.N, p->opH.st_hv, p->nh);
+            hipLaunchKernelGGL(k_relabel, dim3(blocks(p->E.N)), dim3(256), 0, st, kEh, p->nh, p->E.perm, p->E.inv,
+                               p->E.N, p->opE.st_hv, p->nh);
+        }
+    }
+    (void)status;
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
+
+static int launch_weights(rbffd_plan* p, const OpBlock& o, const NodeSet& T, const NodeSet& S, bool curl,
+                          int32_t* status, hipStream_t st) {
+    const int d = p->dim;
+    WArgs a{};
+    a.txyz = T.xyz;
+    a.sxyz = S.xyz;
+    a.d = d;
+    a.periodic = p->p.bc == RBFFD_BC_PERIODIC;
+    for (int k = 0; k < 3; ++k) a.period[k] = p->p.hi[k] - p->p.lo[k];
+    a.Nt = o.Nt;
+    a.status = status;
+    if (curl) {
+        a.st = o.cross ? o.st_curl : o.st_union;
+        a.st_stride = o.cross ? o.n : o.ns;
+        a.n = o.n;
+        a.M = p->M;
+        a.kind = (p->p.mode == RBFFD_MODE_VFD) ? W_VFD : W_FD;
+        a.phs_k = p->p.phs_k;
+        a.nrhs = d;
+        a.upow = 1;
+        a.vdelta = p->p.vfd_sigma * p->p.h;
+        for (int q = 0; q < p->M; ++q)
+            for (int k = 0; k < 3; ++k) a.ex[q][k] = (int8_t)p->ex_m[q][k];
+        a.out = o.wc;
+        a.check_self = !o.cross;
+    } else {
+        const int al = p->p.hv_alpha;
+        a.st = o.cross ? o.st_hv : o.st_union;
+        a.st_stride = o.cross ? o.nh : o.ns;
+        a.n = o.nh;
+        a.M = p->Mh;
+        a.kind = W_HV;
+        a.phs_k = 2 * al + 1;
+        a.nrhs = 1;
+        a.upow = 2 * al;
+        // Delta^alpha r^k = C r^(k - 2 alpha): radial Laplacian k (k + d - 2) r^(k-2), iterated
+        double C = 1.0;
+        for (int t = 0, kk = a.phs_k; t < al; ++t, kk -= 2) C *= (double)kk * (kk + d - 2);
+        a.hv_C = C;
+        for (int q = 0; q < p->Mh; ++q) {
+            for (int k = 0; k < 3; ++k) a.ex[q][k] = (int8_t)p->ex_h[q][k];
+            // Delta^alpha x^a y^b z^c at 0: nonzero only for a = 2i, b = 2j, c = 2l with i + j + l = alpha;
+            // value alpha! / (i! j! l!) * a! b! c!
+            const int* e = p->ex_h[q];
+            double v = 0.0;
+            if (e[0] + e[1] + e[2] == 2 * al && e[0] % 2 == 0 && e[1] % 2 == 0 && e[2] % 2 == 0) {
+                auto fact = [](int x) { double f = 1; for (int i = 2; i <= x; ++i) f *= i; return f; };
+                v = fact(al) / (fact(e[0] / 2) * fact(e[1] / 2) * fact(e[2] / 2)) * fact(e[0]) * fact(e[1]) * fact(e[2]);
+            }
+            a.hv_poly[q] = v;
+        }
+        a.out = o.wh;
+        a.check_self = 1;
+    }
+    const int R = a.n + a.M;
+    const size_t lds = (size_t)(R * (R + a.nrhs) + a.n * 3 + R) * 8;
+    int dev = 0, max_lds = 65536;
+    HIPCHK(p, hipGetDevice(&dev));
+    HIPCHK(p, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (lds + 64 > (size_t)max_lds)
+        return set_err(p, RBFFD_ESIZE, "local system of " + std::to_string(R) + " unknowns needs " +
+                                           std::to_string(lds) + " B of LDS; the device allows " +
+                                           std::to_string(max_lds));
+    hipLaunchKernelGGL(k_weights, dim3((unsigned)o.Nt), dim3(256), lds, st, a);
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
+
+int setup_weights(rbffd_plan* p, void* wsp, hipStream_t st) {
+    WS w{(char*)wsp};
+    int32_t* status = w.take<int32_t>(64);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, status, 64, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, st, status, 1, INT32_MAX);
+    int rc;
+    if (p->collocated) {
+        if ((rc = launch_weights(p, p->opH, p->E, p->E, true, status, st))) return rc;
+        if (p->nh > 0 && (rc = launch_weights(p, p->opH, p->E, p->E, false, status, st))) return rc;
+    } else {
+        if ((rc = launch_weights(p, p->opH, p->H, p->E, true, status, st))) return rc;
+        if (p->nh > 0 && (rc = launch_weights(p, p->opH, p->H, p->H, false, status, st))) return rc;
+        if ((rc = launch_weights(p, p->opE, p->E, p->H, true, status, st))) return rc;
+        if (p->nh > 0 && (rc = launch_weights(p, p->opE, p->E, p->E, false, status, st))) return rc;
+    }
+    return stage_status(p, status, st);
+}
+
+static int pack_block(rbffd_plan* p, const OpBlock& o, hipStream_t st) {
+    const int d = p->dim;
+    const int64_t G = o.tiles * RBFFD_TILE;
+    const bool f64 = p->p.wdtype == RBFFD_F64;
+    if (!o.cross) {
+        if (f64)
+            hipLaunchKernelGGL(k_pack_union<double>, dim3(blocks(G)), dim3(256), 0, st, o.st_union, o.wc, o.wh, o.Nt,
+                               o.ns, o.n, o.nh, d, o.C4, o.V4, o.S4, o.tiles, (int4*)o.pidx, (double*)o.pwc,
+                               (double*)o.pwh);
+        else
+            hipLaunchKernelGGL(k_pack_union<float>, dim3(blocks(G)), dim3(256), 0, st, o.st_union, o.wc, o.wh, o.Nt,
+                               o.ns, o.n, o.nh, d, o.C4, o.V4, o.S4, o.tiles, (int4*)o.pidx, (float*)o.pwc,
+                               (float*)o.pwh);
+        if (p->K > 1)
+            hipLaunchKernelGGL(k_pack_batched, dim3(blocks(o.Nt)), dim3(256), 0, st, o.st_union, o.wc, o.wh, o.Nt, o.ns,
+                               o.n, o.nh, d, o.C4, o.V4, o.S4, o.bidx, o.bwc, o.bwh);
+    } else {
+        if (f64)
+            hipLaunchKernelGGL(k_pack_cross<double>, dim3(blocks(G)), dim3(256), 0, st, o.st_curl, o.st_hv, o.wc, o.wh,
+                               o.Nt, o.n, o.nh, d, o.C4, o.V4, o.tiles, (int4*)o.pidx, (int4*)o.pidx_h, o.pref,
+                               (double*)o.pwc, (double*)o.pwh);
+        else
+            hipLaunchKernelGGL(k_pack_cross<float>, dim3(blocks(G)), dim3(256), 0, st, o.st_curl, o.st_hv, o.wc, o.wh,
+                               o.Nt, o.n, o.nh, d, o.C4, o.V4, o.tiles, (int4*)o.pidx, (int4*)o.pidx_h, o.pref,
+                               (float*)o.pwc, (float*)o.pwh);
+    }
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
+
+int pack_all(rbffd_plan* p, void*, hipStream_t st) {
+    int rc = pack_block(p, p->opH, st);
+    if (rc) return rc;
+    if (!p->collocated) rc = pack_block(p, p->opE, st);
+    return rc;
+}
+
+int build_transpose(rbffd_plan* p, void* wsp, hipStream_t st) {
+    OpBlock& o = p->opH;
+    const int64_t N = o.Nt, ns = o.ns, E = N * ns;
+    WS w{(char*)wsp};
+    uint64_t* kin = w.take<uint64_t>(E);
+    uint64_t* kout = w.take<uint64_t>(E);
+    int32_t* rstart = w.take<int32_t>(N);
+    int32_t* rend = w.take<int32_t>(N);
+    size_t tb = key_sort_temp_bytes(E);
+    void* temp = w.take<char>((int64_t)tb);
+    hipLaunchKernelGGL(k_tkeys, dim3(blocks(E)), dim3(256), 0, st, o.st_union, N, (int)ns, kin);
+    int end_bit = 1;
+    while (end_bit < 64 && ((uint64_t)1 << end_bit) <= (uint64_t)(N * E)) ++end_bit;
+    HIPCHK(p, hipcub::DeviceRadixSort::SortKeys(temp, tb, kin, kout, (int)E, 0, std::min(end_bit + 1, 64), st));
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(N)), dim3(256), 0, st, rstart, N, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(N)), dim3(256), 0, st, rend, N, 0);
+    hipLaunchKernelGGL(k_tdeg, dim3(blocks(E)), dim3(256), 0, st, kout, E, N * ns, rstart, rend);
+    hipLaunchKernelGGL(k_twidth, dim3(blocks(o.tiles)), dim3(256), 0, st, rstart, rend, N, o.tiles, o.t_width);
+    std::vector<int32_t> width(o.tiles);
+    HIPCHK(p, hipMemcpyAsync(width.data(), o.t_width, o.tiles * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+    std::vector<int64_t> off(o.tiles + 1, 0);
+    for (int64_t t = 0; t < o.tiles; ++t) off[t + 1] = off[t] + (int64_t)width[t] * RBFFD_TILE;
+    if (off[o.tiles] > o.t_cap) return set_err(p, RBFFD_ESIZE, "transposed operator exceeds its capacity");
+    HIPCHK(p, hipMemcpyAsync(o.t_off, off.data(), (o.tiles + 1) * 8, hipMemcpyHostToDevice, st));
+    const int64_t G = o.tiles * RBFFD_TILE;
+    if (p->p.wdtype == RBFFD_F64)
+        hipLaunchKernelGGL(k_tfill<double>, dim3(blocks(G)), dim3(256), 0, st, kout, rstart, rend, o.t_off, o.t_width,
+                           o.wc, o.wh, N, (int)ns, o.n, o.nh, o.tiles, o.t_src, (double*)o.t_w);
+    else
+        hipLaunchKernelGGL(k_tfill<float>, dim3(blocks(G)), dim3(256), 0, st, kout, rstart, rend, o.t_off, o.t_width,
+                           o.wc, o.wh, N, (int)ns, o.n, o.nh, o.tiles, o.t_src, (float*)o.t_w);
+    HIPCHK(p, hipGetLastError());
+    HIPCHK(p, hipStreamSynchronize(st));
+    p->opE = p->opH;
+    return RBFFD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Public set-up entry point and the permutation helper
+// ---------------------------------------------------------------------------
+extern "C" int rbffd_weights(rbffd_plan* p, void* arena, void* ws, void* stream) {
+    if (!p || !arena || !ws) return RBFFD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    p->arena = (char*)arena;
+    p->ready = false;
+    int64_t wsb = 0, aws = 0;
+    layout_arena(p, p->arena, &wsb, &aws);
+    int rc = setup_nodes_and_stencils(p, ws, st);
+    if (rc) return rc;
+    if ((rc = setup_weights(p, ws, st))) return rc;
+    if ((rc = pack_all(p, ws, st))) return rc;
+    if (p->p.adjoint && (rc = build_transpose(p, ws, st))) return rc;
+    HIPCHK(p, hipStreamSynchronize(st));
+    p->ready = true;
+    return RBFFD_OK;
+}
+
+__global__ void k_permute(const char* in, char* out, const int32_t* perm, int64_t N, int64_t eb, int to_internal) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t words = eb / 2;
+    if (g >= N * words) return;
+    const int64_t p = g / words, w = g % words;
+    const int64_t o = perm[p];
+    const uint16_t* src = (const uint16_t*)in;
+    uint16_t* dst = (uint16_t*)out;
+    if (to_internal) dst[p * words + w] = src[o * words + w];
+    else dst[o * words + w] = src[p * words + w];
+}
+
+extern "C" int rbffd_permute(const rbffd_plan* p, int32_t set, int32_t to_internal, int64_t eb, const void* in,
+                             void* out, void* stream) {
+    if (!p || !in || !out || eb <= 0 || (eb % 2)) return RBFFD_EINVAL;
+    if (!p->ready) return set_err(p, RBFFD_ESTATE, "rbffd_weights has not run");
+    if (in == out) return set_err(p, RBFFD_EINVAL, "permute cannot work in place");
+    const NodeSet& S = (set == 1 && !p->collocated) ? p->H : p->E;
+    const int64_t n = S.N * (eb / 2);
+    hipLaunchKernelGGL(k_permute, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, (const char*)in, (char*)out,
+                       S.perm, S.N, eb, to_internal);
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}

@@ -1,0 +1,924 @@
+// The hot path: one fused kernel per half step of the stabilised leapfrog
+// (Kolar-Pozun & Kosec, arXiv 2508.18205, Section 5, eq. 19; 3D with the full
+// discrete curl), plus the run driver (sources, receivers, energy of eq. 20,
+// checkpoints, HIP-graph replay) and the FP64 reductions.
+//
+// Per node i the H update is
+//   H_i <- H_i + a (-curl_D E)_i + a gamma (D^hv H)_i          a = dt / mu0
+// and the E update
+//   E_i <- mask_i [ E_i + kappa_i ((curl_D H_new)_i + gamma (D^hv E)_i) ]
+// with kappa_i = dt / (eps0 eps_r,i) and mask = the PEC projector.  All
+// operators are applied in difference form sum_s w_s (f_s - f_ref) with the
+// reference slot left out (the weights sum to zero), which keeps the FP32
+// sums free of the cancellation of sum_s w_s f_s.
+//
+// One wavefront owns one 64-node tile; its lanes stream the tile's packed
+// indices and weights with 16-byte loads and gather field values through the
+// L2 (nodes are Morton ordered, tiles are mapped XCD-contiguously).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "fields.h"
+
+namespace {
+
+template <typename TS, typename TW>
+struct SA {
+    const TS* E;          // E^n
+    const TS* H;          // H update: H^n ; E update: H^{n+1}
+    TS* out;              // H^{n+1} or E^{n+1}
+    const int4* idx;      // collocated: union chunks ; two-set: curl chunks
+    const int4* idx_h;    // two-set: hv chunks
+    const int32_t* pref;  // two-set: curl reference node
+    const TW* wc;
+    const TW* wh;
+    int64_t N, tiles;
+    int C4, V4, S4;
+    int xcd;
+    double a;             // H update: dt / mu0 ; E update: dt / eps0
+    double g;             // gamma
+    double dt, eps0;
+    const void* eps_r;    // per-node eps_r (double for FP64 fields, else float) or null
+    const uint8_t* emask;
+};
+
+template <typename TS, typename TW>
+__device__ __forceinline__ int64_t tile_of(const SA<TS, TW>& a) {
+    const int wpb = blockDim.x >> 6;
+    const int blk = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    return (int64_t)blk * wpb + (threadIdx.x >> 6);
+}
+
+template <typename TS, typename TW>
+__device__ __forceinline__ typename Store<TS>::C kappa_of(const SA<TS, TW>& a, int64_t i) {
+    using TC = typename Store<TS>::C;
+    if (!a.eps_r) return (TC)a.a;
+    if (sizeof(TC) == 8) return (TC)(a.dt / (a.eps0 * ((const double*)a.eps_r)[i]));
+    return (TC)(a.dt / (a.eps0 * (double)((const float*)a.eps_r)[i]));
+}
+
+// ---- 2D TMz, collocated ----------------------------------------------------
+template <typename TS, typename TW>
+__global__ __launch_bounds__(512) void k_h2(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    const int64_t tile = tile_of(a);
+    if (tile >= a.tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    const TC e0 = S::ld1(a.E, ic);
+    TC hx0, hy0;
+    S::ld2(a.H, ic, hx0, hy0);
+    TC dx = 0, dy = 0, vx = 0, vy = 0;
+    const int4* pi = a.idx + tile * a.S4 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const int qb = min(a.C4, a.V4);
+    int q = 0;
+    for (; q < qb; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4], wh[4];
+        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+        ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int jj = idx4(j, u);
+            const TC de = S::ld1(a.E, jj) - e0;
+            dx += (TC)wx[u] * de;
+            dy += (TC)wy[u] * de;
+            TC hx, hy;
+            S::ld2(a.H, jj, hx, hy);
+            vx += (TC)wh[u] * (hx - hx0);
+            vy += (TC)wh[u] * (hy - hy0);
+        }
+    }
+    for (; q < a.C4; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4];
+        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const TC de = S::ld1(a.E, idx4(j, u)) - e0;
+            dx += (TC)wx[u] * de;
+            dy += (TC)wy[u] * de;
+        }
+    }
+    for (; q < a.V4; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wh[4];
+        ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC hx, hy;
+            S::ld2(a.H, idx4(j, u), hx, hy);
+            vx += (TC)wh[u] * (hx - hx0);
+            vy += (TC)wh[u] * (hy - hy0);
+        }
+    }
+    if (i < a.N) {
+        const TC A = (TC)a.a, G = (TC)a.g;
+        S::st2(a.out, i, hx0 + A * (-dy + G * vx), hy0 + A * (dx + G * vy));
+    }
+}
+
+template <typename TS, typename TW>
+__global__ __launch_bounds__(512) void k_e2(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    const int64_t tile = tile_of(a);
+    if (tile >= a.tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    const TC e0 = S::ld1(a.E, ic);
+    TC hx0, hy0;
+    S::ld2(a.H, ic, hx0, hy0);
+    TC cu = 0, ve = 0;
+    const int4* pi = a.idx + tile * a.S4 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const int qb = min(a.C4, a.V4);
+    int q = 0;
+    for (; q < qb; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4], wh[4];
+        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+        ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int jj = idx4(j, u);
+            TC hx, hy;
+            S::ld2(a.H, jj, hx, hy);
+            cu += (TC)wx[u] * (hy - hy0) - (TC)wy[u] * (hx - hx0);
+            ve += (TC)wh[u] * (S::ld1(a.E, jj) - e0);
+        }
+    }
+    for (; q < a.C4; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4];
+        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC hx, hy;
+            S::ld2(a.H, idx4(j, u), hx, hy);
+            cu += (TC)wx[u] * (hy - hy0) - (TC)wy[u] * (hx - hx0);
+        }
+    }
+    for (; q < a.V4; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wh[4];
+        ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ve += (TC)wh[u] * (S::ld1(a.E, idx4(j, u)) - e0);
+    }
+    if (i < a.N) {
+        const TC k = kappa_of(a, i);
+        const TC v = (a.emask[i] & 1) ? e0 + k * (cu + (TC)a.g * ve) : (TC)0;
+        S::st1(a.out, i, v);
+    }
+}
+
+// ---- 2D TMz, two node sets ---------------------------------------------------
+// H update: curl of E from the E set (reference = nearest E node), HV of H on
+// the H set.  E update: curl of H from the H set, HV of E on the E set.
+template <typename TS, typename TW>
+__global__ __launch_bounds__(512) void k_h2x(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    const int64_t tile = tile_of(a);
+    if (tile >= a.tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    const TC e0 = S::ld1(a.E, a.pref[ic]);
+    TC hx0, hy0;
+    S::ld2(a.H, ic, hx0, hy0);
+    TC dx = 0, dy = 0, vx = 0, vy = 0;
+    const int4* pi = a.idx + tile * a.C4 * RBFFD_TILE + lane;
+    const int4* pj = a.idx_h + tile * a.V4 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    for (int q = 0; q < a.C4; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4];
+        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const TC de = S::ld1(a.E, idx4(j, u)) - e0;
+            dx += (TC)wx[u] * de;
+            dy += (TC)wy[u] * de;
+        }
+    }
+    for (int q = 0; q < a.V4; ++q) {
+        const int4 j = pj[q * RBFFD_TILE];
+        TW wh[4];
+        ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC hx, hy;
+            S::ld2(a.H, idx4(j, u), hx, hy);
+            vx += (TC)wh[u] * (hx - hx0);
+            vy += (TC)wh[u] * (hy - hy0);
+        }
+    }
+    if (i < a.N) {
+        const TC A = (TC)a.a, G = (TC)a.g;
+        S::st2(a.out, i, hx0 + A * (-dy + G * vx), hy0 + A * (dx + G * vy));
+    }
+}
+
+template <typename TS, typename TW>
+__global__ __launch_bounds__(512) void k_e2x(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    const int64_t tile = tile_of(a);
+    if (tile >= a.tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    const TC e0 = S::ld1(a.E, ic);
+    TC hx0, hy0;
+    S::ld2(a.H, a.pref[ic], hx0, hy0);
+    TC cu = 0, ve = 0;
+    const int4* pi = a.idx + tile * a.C4 * RBFFD_TILE + lane;
+    const int4* pj = a.idx_h + tile * a.V4 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    for (int q = 0; q < a.C4; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4];
+        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC hx, hy;
+            S::ld2(a.H, idx4(j, u), hx, hy);
+            cu += (TC)wx[u] * (hy - hy0) - (TC)wy[u] * (hx - hx0);
+        }
+    }
+    for (int q = 0; q < a.V4; ++q) {
+        const int4 j = pj[q * RBFFD_TILE];
+        TW wh[4];
+        ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ve += (TC)wh[u] * (S::ld1(a.E, idx4(j, u)) - e0);
+    }
+    if (i < a.N) {
+        const TC k = kappa_of(a, i);
+        const TC v = (a.emask[i] & 1) ? e0 + k * (cu + (TC)a.g * ve) : (TC)0;
+        S::st1(a.out, i, v);
+    }
+}
+
+// ---- 3D, collocated: E and H stored as (x, y, z, pad) -------------------------
+template <typename TS, typename TW>
+__global__ __launch_bounds__(512) void k_h3(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    const int64_t tile = tile_of(a);
+    if (tile >= a.tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    TC ex0, ey0, ez0, hx0, hy0, hz0;
+    S::ld3(a.E, ic, ex0, ey0, ez0);
+    S::ld3(a.H, ic, hx0, hy0, hz0);
+    // d_a E_c accumulators for the curl
+    TC xEy = 0, xEz = 0, yEx = 0, yEz = 0, zEx = 0, zEy = 0, vx = 0, vy = 0, vz = 0;
+    const int4* pi = a.idx + tile * a.S4 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tile * a.C4 * 3 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const int qb = min(a.C4, a.V4);
+    int q = 0;
+    for (; q < qb; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4], wz[4], wh[4];
+        ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
+        ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
+        ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
+        ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int jj = idx4(j, u);
+            TC ex, ey, ez, hx, hy, hz;
+            S::ld3(a.E, jj, ex, ey, ez);
+            S::ld3(a.H, jj, hx, hy, hz);
+            ex -= ex0; ey -= ey0; ez -= ez0;
+            xEy += (TC)wx[u] * ey; xEz += (TC)wx[u] * ez;
+            yEx += (TC)wy[u] * ex; yEz += (TC)wy[u] * ez;
+            zEx += (TC)wz[u] * ex; zEy += (TC)wz[u] * ey;
+            vx += (TC)wh[u] * (hx - hx0);
+            vy += (TC)wh[u] * (hy - hy0);
+            vz += (TC)wh[u] * (hz - hz0);
+        }
+    }
+    for (; q < a.C4; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4], wz[4];
+        ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
+        ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
+        ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC ex, ey, ez;
+            S::ld3(a.E, idx4(j, u), ex, ey, ez);
+            ex -= ex0; ey -= ey0; ez -= ez0;
+            xEy += (TC)wx[u] * ey; xEz += (TC)wx[u] * ez;
+            yEx += (TC)wy[u] * ex; yEz += (TC)wy[u] * ez;
+            zEx += (TC)wz[u] * ex; zEy += (TC)wz[u] * ey;
+        }
+    }
+    for (; q < a.V4; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wh[4];
+        ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC hx, hy, hz;
+            S::ld3(a.H, idx4(j, u), hx, hy, hz);
+            vx += (TC)wh[u] * (hx - hx0);
+            vy += (TC)wh[u] * (hy - hy0);
+            vz += (TC)wh[u] * (hz - hz0);
+        }
+    }
+    if (i < a.N) {
+        const TC A = (TC)a.a, G = (TC)a.g;
+        // H <- H - a (curl E - gamma D^hv H)
+        S::st3(a.out, i, hx0 - A * ((yEz - zEy) - G * vx), hy0 - A * ((zEx - xEz) - G * vy),
+               hz0 - A * ((xEy - yEx) - G * vz));
+    }
+}
+
+template <typename TS, typename TW>
+__global__ __launch_bounds__(512) void k_e3(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    const int64_t tile = tile_of(a);
+    if (tile >= a.tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    TC ex0, ey0, ez0, hx0, hy0, hz0;
+    S::ld3(a.E, ic, ex0, ey0, ez0);
+    S::ld3(a.H, ic, hx0, hy0, hz0);
+    TC xHy = 0, xHz = 0, yHx = 0, yHz = 0, zHx = 0, zHy = 0, vx = 0, vy = 0, vz = 0;
+    const int4* pi = a.idx + tile * a.S4 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tile * a.C4 * 3 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const int qb = min(a.C4, a.V4);
+    int q = 0;
+    for (; q < qb; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4], wz[4], wh[4];
+        ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
+        ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
+        ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
+        ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int jj = idx4(j, u);
+            TC ex, ey, ez, hx, hy, hz;
+            S::ld3(a.H, jj, hx, hy, hz);
+            S::ld3(a.E, jj, ex, ey, ez);
+            hx -= hx0; hy -= hy0; hz -= hz0;
+            xHy += (TC)wx[u] * hy; xHz += (TC)wx[u] * hz;
+            yHx += (TC)wy[u] * hx; yHz += (TC)wy[u] * hz;
+            zHx += (TC)wz[u] * hx; zHy += (TC)wz[u] * hy;
+            vx += (TC)wh[u] * (ex - ex0);
+            vy += (TC)wh[u] * (ey - ey0);
+            vz += (TC)wh[u] * (ez - ez0);
+        }
+    }
+    for (; q < a.C4; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4], wz[4];
+        ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
+        ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
+        ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC hx, hy, hz;
+            S::ld3(a.H, idx4(j, u), hx, hy, hz);
+            hx -= hx0; hy -= hy0; hz -= hz0;
+            xHy += (TC)wx[u] * hy; xHz += (TC)wx[u] * hz;
+            yHx += (TC)wy[u] * hx; yHz += (TC)wy[u] * hz;
+            zHx += (TC)wz[u] * hx; zHy += (TC)wz[u] * hy;
+        }
+    }
+    for (; q < a.V4; ++q) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wh[4];
+        ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC ex, ey, ez;
+            S::ld3(a.E, idx4(j, u), ex, ey, ez);
+            vx += (TC)wh[u] * (ex - ex0);
+            vy += (TC)wh[u] * (ey - ey0);
+            vz += (TC)wh[u] * (ez - ez0);
+        }
+    }
+    if (i < a.N) {
+        const TC k = kappa_of(a, i), G = (TC)a.g;
+        const uint8_t m = a.emask[i];
+        const TC nx = (m & 1) ? ex0 + k * ((yHz - zHy) + G * vx) : (TC)0;
+        const TC ny = (m & 2) ? ey0 + k * ((zHx - xHz) + G * vy) : (TC)0;
+        const TC nz = (m & 4) ? ez0 + k * ((xHy - yHx) + G * vz) : (TC)0;
+        S::st3(a.out, i, nx, ny, nz);
+    }
+}
+
+// ---- per-step auxiliaries (read the device step counter) --------------------
+// src: E[node] += amp * wave[n * S + s] after the bracket (PEC nodes stay 0)
+template <typename TS>
+__global__ void k_source(TS* E, int FE, int comp, const uint8_t* emask, int S, const int32_t* node, const void* amp,
+                         const void* wave, const int32_t* ctr, int step_base) {
+    using St = Store<TS>;
+    using TC = typename St::C;
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t n = (int64_t)(*ctr) + step_base;
+    for (int s = 0; s < S; ++s) {
+        const int64_t i = node[s];
+        const int64_t e = i * FE + comp;
+        TC v;
+        if (sizeof(TC) == 8) v = ((const double*)amp)[s] * ((const double*)wave)[n * S + s];
+        else v = ((const float*)amp)[s] * ((const float*)wave)[n * S + s];
+        const TC cur = St::ld1(E, e);
+        St::st1(E, e, ((emask[i] >> comp) & 1) ? cur + v : (TC)0);
+    }
+}
+
+template <typename TS>
+__global__ void k_receivers(const TS* E, int FE, int comp, int R, const int32_t* node, void* traces, const int32_t* ctr,
+                            int T) {
+    using St = Store<TS>;
+    using TC = typename St::C;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = *ctr;
+    if (r >= R || n >= T) return;
+    const TC v = St::ld1(E, (int64_t)node[r] * FE + comp);
+    if (sizeof(TC) == 8) ((double*)traces)[(int64_t)n * R + r] = (double)v;
+    else ((float*)traces)[(int64_t)n * R + r] = (float)v;
+}
+
+__global__ void k_ctr_set(int32_t* ctr, int32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = v;
+}
+__global__ void k_ctr_inc(int32_t* ctr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += 1;
+}
+
+// checkpoint: copy (E, H) into slot n / every when n % every == 0 (2-byte units)
+__global__ void k_ckpt(const uint16_t* E, int64_t e2, const uint16_t* H, int64_t h2, char* ck, int64_t slot_bytes,
+                       int every, const int32_t* ctr) {
+    const int n = *ctr;
+    if (n % every) return;
+    uint16_t* dst = (uint16_t*)(ck + (int64_t)(n / every) * slot_bytes);
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < e2 + h2; g += (int64_t)gridDim.x * blockDim.x)
+        dst[g] = g < e2 ? E[g] : H[g - e2];
+}
+
+// ---- FP64 reductions --------------------------------------------------------
+constexpr int RED_BLOCKS = 1024;
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_energy1(const TS* E, int64_t NE, int FE, int fe, const TS* Ha, const TS* Hb,
+                                                 int64_t NH, int FH, int fh, double wE, double wH, double* part,
+                                                 const int32_t* ctr, int every) {
+    using St = Store<TS>;
+    if (ctr && (*ctr % every)) return;
+    __shared__ double sh[256];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NE; i += stride)
+        for (int c = 0; c < fe; ++c) {
+            const double v = (double)St::ld1(E, i * FE + c);
+            acc += wE * v * v;
+        }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NH; i += stride)
+        for (int c = 0; c < fh; ++c) {
+            const double v = 0.5 * ((double)St::ld1(Ha, i * FH + c) + (double)St::ld1(Hb, i * FH + c));
+            acc += wH * v * v;
+        }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce2(const double* part, int nparts, double* out, const int32_t* ctr,
+                                                 int every) {
+    if (ctr && (*ctr % every)) return;
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[ctr ? (*ctr / every) : 0] = sh[0];
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_compare1(const TS* F, int64_t N, int FS, int nc, const double* ref,
+                                                  double* part) {
+    using St = Store<TS>;
+    __shared__ double sh[3][256];
+    double se[4] = {0, 0, 0, 0}, sr[4] = {0, 0, 0, 0}, mx[4] = {0, 0, 0, 0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride)
+        for (int c = 0; c < nc; ++c) {
+            const double f = (double)St::ld1(F, i * FS + c), r = ref[i * nc + c];
+            const double e = f - r;
+            se[c] += e * e;
+            sr[c] += r * r;
+            mx[c] = fmax(mx[c], fabs(e));
+        }
+    for (int c = 0; c < nc; ++c) {
+        sh[0][threadIdx.x] = se[c];
+        sh[1][threadIdx.x] = sr[c];
+        sh[2][threadIdx.x] = mx[c];
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (threadIdx.x < s) {
+                sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+                sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+                sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + s]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            part[(blockIdx.x * nc + c) * 3 + 0] = sh[0][0];
+            part[(blockIdx.x * nc + c) * 3 + 1] = sh[1][0];
+            part[(blockIdx.x * nc + c) * 3 + 2] = sh[2][0];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_compare2(const double* part, int nb, int nc, double* out) {
+    const int c = threadIdx.x;
+    if (c >= nc) return;
+    double se = 0, sr = 0, mx = 0;
+    for (int b = 0; b < nb; ++b) {
+        se += part[(b * nc + c) * 3 + 0];
+        sr += part[(b * nc + c) * 3 + 1];
+        mx = fmax(mx, part[(b * nc + c) * 3 + 2]);
+    }
+    out[c * 3 + 0] = se;
+    out[c * 3 + 1] = sr;
+    out[c * 3 + 2] = mx;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side: launching one half step of either kind
+// ---------------------------------------------------------------------------
+namespace {
+
+struct RunWS {
+    double* part;       // [RED_BLOCKS * 12]
+    int32_t* ctr;
+    double* misc;
+};
+
+RunWS run_ws(void* ws) {
+    RunWS w;
+    char* b = (char*)ws;
+    w.part = (double*)b;
+    w.ctr = (int32_t*)(b + RED_BLOCKS * 12 * 8);
+    w.misc = (double*)(b + RED_BLOCKS * 12 * 8 + 256);
+    return w;
+}
+
+template <typename TS, typename TW>
+void fill_sa(const rbffd_plan* p, const OpBlock& o, SA<TS, TW>& a, bool hupd) {
+    a.idx = (const int4*)o.pidx;
+    a.idx_h = (const int4*)o.pidx_h;
+    a.pref = o.pref;
+    a.wc = (const TW*)o.pwc;
+    a.wh = (const TW*)o.pwh;
+    a.N = o.Nt;
+    a.tiles = o.tiles;
+    a.C4 = o.C4;
+    a.V4 = o.V4;
+    a.S4 = o.S4;
+    a.xcd = p->var.xcd;
+    a.g = p->gamma;
+    a.dt = p->dt;
+    a.eps0 = p->p.eps0;
+    a.a = hupd ? p->dt / p->p.mu0 : p->dt / p->p.eps0;
+    a.emask = p->E.emask;
+}
+
+template <typename TS, typename TW>
+void launch_half(const rbffd_plan* p, bool hupd, const void* E, const void* H, void* out, const void* eps_r,
+                 hipStream_t st) {
+    const OpBlock& o = hupd ? p->opH : p->opE;
+    SA<TS, TW> a{};
+    fill_sa(p, o, a, hupd);
+    a.E = (const TS*)E;
+    a.H = (const TS*)H;
+    a.out = (TS*)out;
+    a.eps_r = hupd ? nullptr : eps_r;
+    const int wpb = p->var.block / 64;
+    const dim3 grid((unsigned)cdiv(o.tiles, wpb)), block(p->var.block);
+    if (p->dim == 2) {
+        if (p->collocated) {
+            if (hupd) hipLaunchKernelGGL((k_h2<TS, TW>), grid, block, 0, st, a);
+            else hipLaunchKernelGGL((k_e2<TS, TW>), grid, block, 0, st, a);
+        } else {
+            if (hupd) hipLaunchKernelGGL((k_h2x<TS, TW>), grid, block, 0, st, a);
+            else hipLaunchKernelGGL((k_e2x<TS, TW>), grid, block, 0, st, a);
+        }
+    } else {
+        if (hupd) hipLaunchKernelGGL((k_h3<TS, TW>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_e3<TS, TW>), grid, block, 0, st, a);
+    }
+}
+
+void half(const rbffd_plan* p, bool hupd, const void* E, const void* H, void* out, const void* eps_r, hipStream_t st) {
+    switch (p->p.fdtype) {
+        case RBFFD_F64: launch_half<double, double>(p, hupd, E, H, out, eps_r, st); break;
+        case RBFFD_F32: launch_half<float, float>(p, hupd, E, H, out, eps_r, st); break;
+        default: launch_half<bf16s, float>(p, hupd, E, H, out, eps_r, st); break;
+    }
+}
+
+template <typename TS>
+void launch_energy(const rbffd_plan* p, const void* E, const void* Ha, const void* Hb, double* out, RunWS& w,
+                   const int32_t* ctr, int every, hipStream_t st) {
+    const double wE = std::pow(p->E.h, p->dim);
+    const double hh = p->collocated ? p->E.h : p->H.h;
+    const double wH = p->eta0 * p->eta0 * std::pow(hh, p->dim);
+    const int64_t nmax = std::max(p->E.N, p->H.N);
+    const int nb = (int)std::min<int64_t>(RED_BLOCKS, cdiv(nmax, 256));
+    hipLaunchKernelGGL(k_energy1<TS>, dim3(nb), dim3(256), 0, st, (const TS*)E, p->E.N, p->FE, p->fe_comp,
+                       (const TS*)Ha, (const TS*)Hb, p->H.N, p->FH, p->fh_comp, wE, wH, w.part, ctr, every);
+    hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, st, w.part, nb, out, ctr, every);
+}
+
+void energy(const rbffd_plan* p, const void* E, const void* Ha, const void* Hb, double* out, RunWS& w,
+            const int32_t* ctr, int every, hipStream_t st) {
+    switch (p->p.fdtype) {
+        case RBFFD_F64: launch_energy<double>(p, E, Ha, Hb, out, w, ctr, every, st); break;
+        case RBFFD_F32: launch_energy<float>(p, E, Ha, Hb, out, w, ctr, every, st); break;
+        default: launch_energy<bf16s>(p, E, Ha, Hb, out, w, ctr, every, st); break;
+    }
+}
+
+int check_fields(const rbffd_plan* p, const rbffd_fields* f) {
+    if (!f) return set_err(p, RBFFD_EINVAL, "null fields");
+    if (!p->ready) return set_err(p, RBFFD_ESTATE, "rbffd_weights has not run");
+    if (f->cur != 0 && f->cur != 1) return set_err(p, RBFFD_EINVAL, "fields.cur must be 0 or 1");
+    for (int b = 0; b < 2; ++b)
+        if (!f->E[b] || !f->H[b]) return set_err(p, RBFFD_EINVAL, "null field buffer");
+    if (f->E[0] == f->E[1] || f->H[0] == f->H[1]) return set_err(p, RBFFD_EINVAL, "ping-pong buffers must differ");
+    return RBFFD_OK;
+}
+
+}  // namespace
+
+// K-field batch (batched.hip)
+int batched_step(const rbffd_plan* p, rbffd_fields* f, int32_t nsteps, hipStream_t st);
+
+extern "C" int rbffd_step(const rbffd_plan* p, rbffd_fields* f, int32_t nsteps, void* stream) {
+    if (!p) return RBFFD_EINVAL;
+    int rc = check_fields(p, f);
+    if (rc) return rc;
+    if (nsteps < 0) return set_err(p, RBFFD_EINVAL, "nsteps < 0");
+    hipStream_t st = (hipStream_t)stream;
+    if (p->K > 1) return batched_step(p, f, nsteps, st);
+    for (int s = 0; s < nsteps; ++s) {
+        const int c = f->cur, o = 1 - c;
+        half(p, true, f->E[c], f->H[c], f->H[o], nullptr, st);
+        half(p, false, f->E[c], f->H[o], f->E[o], f->eps_r, st);
+        f->cur = o;
+    }
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
+
+extern "C" int rbffd_half(const rbffd_plan* p, const rbffd_fields* f, int32_t which, void* stream) {
+    if (!p) return RBFFD_EINVAL;
+    int rc = check_fields(p, f);
+    if (rc) return rc;
+    if (p->K > 1) return set_err(p, RBFFD_ENOTSUP, "rbffd_half is for single-field plans");
+    if (which != 0 && which != 1) return set_err(p, RBFFD_EINVAL, "which must be 0 (H) or 1 (E)");
+    const int c = f->cur, o = 1 - c;
+    if (which == 0) half(p, true, f->E[c], f->H[c], f->H[o], nullptr, (hipStream_t)stream);
+    else half(p, false, f->E[c], f->H[o], f->E[o], f->eps_r, (hipStream_t)stream);
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
+
+namespace {
+// One full step with every auxiliary; buffers (c -> o) fixed so it can be
+// captured.  The device counter holds the step index.
+void full_step(const rbffd_plan* p, const rbffd_fields* f, int c, const rbffd_run_args* a, RunWS& w, hipStream_t st) {
+    const int o = 1 - c;
+    const int comp = p->dim == 2 ? 0 : 2;
+    if (a->ckpt) {
+        const int64_t eb = p->E.N * p->FE * (int64_t)field_elem_bytes(p->p.fdtype);
+        const int64_t hb = p->H.N * p->FH * (int64_t)field_elem_bytes(p->p.fdtype);
+        hipLaunchKernelGGL(k_ckpt, dim3(1024), dim3(256), 0, st, (const uint16_t*)f->E[c], eb / 2,
+                           (const uint16_t*)f->H[c], hb / 2, (char*)a->ckpt, eb + hb, a->ckpt_every,
+                           (const int32_t*)w.ctr);
+    }
+    half(p, true, f->E[c], f->H[c], f->H[o], nullptr, st);
+    if (a->energy_out && a->energy_every > 0)
+        energy(p, f->E[c], f->H[c], f->H[o], a->energy_out, w, w.ctr, a->energy_every, st);
+    half(p, false, f->E[c], f->H[o], f->E[o], f->eps_r, st);
+    if (a->n_src > 0) {
+        switch (p->p.fdtype) {
+            case RBFFD_F64:
+                hipLaunchKernelGGL(k_source<double>, dim3(1), dim3(64), 0, st, (double*)f->E[o], p->FE, comp, p->E.emask,
+                                   a->n_src, a->src_node, a->src_amp, a->src_wave, w.ctr, a->step0);
+                break;
+            case RBFFD_F32:
+                hipLaunchKernelGGL(k_source<float>, dim3(1), dim3(64), 0, st, (float*)f->E[o], p->FE, comp, p->E.emask,
+                                   a->n_src, a->src_node, a->src_amp, a->src_wave, w.ctr, a->step0);
+                break;
+            default:
+                hipLaunchKernelGGL(k_source<bf16s>, dim3(1), dim3(64), 0, st, (bf16s*)f->E[o], p->FE, comp,
+                                   p->E.emask, a->n_src, a->src_node, a->src_amp, a->src_wave, w.ctr, a->step0);
+        }
+    }
+    if (a->n_rcv > 0) {
+        const dim3 g((unsigned)cdiv(a->n_rcv, 64));
+        switch (p->p.fdtype) {
+            case RBFFD_F64:
+                hipLaunchKernelGGL(k_receivers<double>, g, dim3(64), 0, st, (const double*)f->E[o], p->FE, comp,
+                                   a->n_rcv, a->rcv_node, a->traces, w.ctr, a->T);
+                break;
+            case RBFFD_F32:
+                hipLaunchKernelGGL(k_receivers<float>, g, dim3(64), 0, st, (const float*)f->E[o], p->FE, comp, a->n_rcv,
+                                   a->rcv_node, a->traces, w.ctr, a->T);
+                break;
+            default:
+                hipLaunchKernelGGL(k_receivers<bf16s>, g, dim3(64), 0, st, (const bf16s*)f->E[o], p->FE, comp,
+                                   a->n_rcv, a->rcv_node, a->traces, w.ctr, a->T);
+        }
+    }
+    hipLaunchKernelGGL(k_ctr_inc, dim3(1), dim3(64), 0, st, w.ctr);
+}
+}  // namespace
+
+int batched_run(const rbffd_plan* p, rbffd_fields* f, const rbffd_run_args* a, void* ws, hipStream_t st);
+
+extern "C" int rbffd_run(const rbffd_plan* p, rbffd_fields* f, const rbffd_run_args* a, void* ws, void* stream) {
+    if (!p || !a) return RBFFD_EINVAL;
+    int rc = check_fields(p, f);
+    if (rc) return rc;
+    if (!ws) return set_err(p, RBFFD_EINVAL, "run needs the workspace");
+    if (a->T < 0) return set_err(p, RBFFD_EINVAL, "T < 0");
+    hipStream_t st = (hipStream_t)stream;
+    if (p->K > 1) return batched_run(p, f, a, ws, st);
+    if (a->n_src > 0 && (!a->src_node || !a->src_amp || !a->src_wave))
+        return set_err(p, RBFFD_EINVAL, "sources need node, amplitude and waveform arrays");
+    if (a->n_rcv > 0 && (!a->rcv_node || !a->traces)) return set_err(p, RBFFD_EINVAL, "receivers need nodes and traces");
+    if (a->ckpt && a->ckpt_every <= 0) return set_err(p, RBFFD_EINVAL, "ckpt_every must be positive");
+    if (a->energy_out && a->energy_every < 0) return set_err(p, RBFFD_EINVAL, "energy_every < 0");
+    const int64_t eb = p->E.N * p->FE * (int64_t)field_elem_bytes(p->p.fdtype);
+    const int64_t hb = p->H.N * p->FH * (int64_t)field_elem_bytes(p->p.fdtype);
+    RunWS w = run_ws(ws);
+    hipLaunchKernelGGL(k_ctr_set, dim3(1), dim3(64), 0, st, w.ctr, 0);
+    int s = 0;
+    if (a->use_graph && a->T >= 4) {
+        // capture two steps (c -> o -> c) and replay; buffers return to their roles
+        hipGraph_t g;
+        hipGraphExec_t ge;
+        hipStream_t cs;
+        if ((rc = capture_stream(p, &cs))) return rc;
+        HIPCHK(p, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        full_step(p, f, f->cur, a, w, cs);
+        full_step(p, f, 1 - f->cur, a, w, cs);
+        HIPCHK(p, hipStreamEndCapture(cs, &g));
+        HIPCHK(p, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        for (; s + 2 <= a->T; s += 2) HIPCHK(p, hipGraphLaunch(ge, st));
+        HIPCHK(p, hipGraphExecDestroy(ge));
+        HIPCHK(p, hipGraphDestroy(g));
+    }
+    int c = f->cur;
+    if (s > 0 && (s % 2)) c = 1 - c;
+    for (; s < a->T; ++s) {
+        full_step(p, f, c, a, w, st);
+        c = 1 - c;
+    }
+    f->cur = (a->T % 2) ? 1 - f->cur : f->cur;
+    HIPCHK(p, hipGetLastError());
+    if (a->energy_out && a->energy_every > 0 && a->unstable_threshold > 0 && a->T > 0) {
+        const int ne = (a->T - 1) / a->energy_every + 1;
+        std::vector<double> e(ne);
+        HIPCHK(p, hipMemcpyAsync(e.data(), a->energy_out, ne * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+        for (int k = 0; k < ne; ++k)
+            if (!std::isfinite(e[k]) || e[k] > a->unstable_threshold * e[0])
+                return set_err(p, RBFFD_EUNSTABLE, "energy sample " + std::to_string(k) + " = " + std::to_string(e[k]) +
+                                                       " exceeds the threshold");
+    }
+    return RBFFD_OK;
+}
+
+extern "C" int rbffd_energy(const rbffd_plan* p, const void* E, const void* Ha, const void* Hb, double* out, void* ws,
+                            void* stream) {
+    if (!p || !E || !Ha || !Hb || !out || !ws) return RBFFD_EINVAL;
+    if (!p->ready) return set_err(p, RBFFD_ESTATE, "rbffd_weights has not run");
+    if (p->K > 1) return set_err(p, RBFFD_ENOTSUP, "energy of a K-field batch: use rbffd_compare per field");
+    RunWS w = run_ws(ws);
+    energy(p, E, Ha, Hb, out, w, nullptr, 1, (hipStream_t)stream);
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
+
+extern "C" int rbffd_compare(const rbffd_plan* p, int32_t which, const void* F, const double* ref, double* out,
+                             void* ws, void* stream) {
+    if (!p || !F || !ref || !out || !ws) return RBFFD_EINVAL;
+    if (!p->ready) return set_err(p, RBFFD_ESTATE, "rbffd_weights has not run");
+    hipStream_t st = (hipStream_t)stream;
+    RunWS w = run_ws(ws);
+    const bool isE = which == 0;
+    const int64_t N = (isE ? p->E.N : p->H.N) * (p->K > 1 ? 1 : 1);
+    int FS = isE ? p->FE : p->FH;
+    int nc = isE ? p->fe_comp : p->fh_comp;
+    int64_t rows = N;
+    if (p->K > 1) {
+        // batch layout [N][F][K]: compare every (node, comp, k) value as its own row
+        rows = N * nc * p->K;
+        FS = 1;
+        nc = 1;
+    }
+    const int nb = (int)std::min<int64_t>(RED_BLOCKS, cdiv(rows, 256));
+    switch (p->p.fdtype) {
+        case RBFFD_F64:
+            hipLaunchKernelGGL(k_compare1<double>, dim3(nb), dim3(256), 0, st, (const double*)F, rows, FS, nc, ref, w.part);
+            break;
+        case RBFFD_F32:
+            hipLaunchKernelGGL(k_compare1<float>, dim3(nb), dim3(256), 0, st, (const float*)F, rows, FS, nc, ref, w.part);
+            break;
+        default:
+            hipLaunchKernelGGL(k_compare1<bf16s>, dim3(nb), dim3(256), 0, st, (const bf16s*)F, rows, FS, nc, ref, w.part);
+    }
+    hipLaunchKernelGGL(k_compare2, dim3(1), dim3(64), 0, st, w.part, nb, nc, out);
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch tuning: workgroup size and the XCD remap, timed on the device
+// ---------------------------------------------------------------------------
+extern "C" int rbffd_autotune(rbffd_plan* p, rbffd_fields* f, int32_t reps, void* stream) {
+    if (!p) return RBFFD_EINVAL;
+    int rc = check_fields(p, f);
+    if (rc) return rc;
+    if (reps < 1) reps = 1;
+    hipStream_t st = (hipStream_t)stream;
+    const int blocks_[4] = {64, 128, 256, 512};
+    Variant best = p->var;
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    HIPCHK(p, hipEventCreate(&e0));
+    HIPCHK(p, hipEventCreate(&e1));
+    // single field: workgroup size x XCD remap; K-field batch: workgroup size
+    // (<= 256) x resident workgroups per CU
+    const int persist_[3] = {4, 8, 16};
+    for (int x = 0; x < (p->K > 1 ? 3 : 2); ++x)
+        for (int b : blocks_) {
+            if (p->K > 1 && b > 256) continue;
+            p->var.block = b;
+            if (p->K > 1) p->var.persist = persist_[x];
+            else p->var.xcd = x;
+            rc = rbffd_step(p, f, 2, stream);   // warm
+            if (rc) break;
+            HIPCHK(p, hipEventRecord(e0, st));
+            rc = rbffd_step(p, f, reps, stream);
+            if (rc) break;
+            HIPCHK(p, hipEventRecord(e1, st));
+            HIPCHK(p, hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(p, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = p->var;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->var = best;
+    return rc;
+}

@@ -1,0 +1,79 @@
+"""The C-ABI library loads, exports every declared symbol, and validates plans
+on the host (no GPU calls)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rbffd.h")
+
+
+def _lib():
+    from paper_2508_18205_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.skip("librbffd.so not built")
+    return _abi, _abi.load()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rbffd_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    _abi, lib = _lib()
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _abi.PROTOTYPES, n
+
+
+def test_struct_layouts_match_header_sizes():
+    _abi, _ = _lib()
+    # params: 14 int32 + 7 doubles + 6 doubles
+    assert C.sizeof(_abi.Params) == 14 * 4 + 13 * 8
+    assert C.sizeof(_abi.Fields) == 5 * 8 + 8
+
+
+def _params(_abi, **kw):
+    p = _abi.Params()
+    p.dim, p.mode, p.n, p.m, p.phs_k, p.hv_alpha = 2, 0, 12, 2, 3, 2
+    p.bc, p.reorder, p.wdtype, p.fdtype, p.K = 0, 1, 0, 0, 1
+    p.vfd_sigma, p.hv_c, p.h, p.eps0, p.mu0 = 0.5, 1.0, 0.1, 1.0, 1.0
+    p.hi[0] = p.hi[1] = 1.0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_plan_validation_and_sizes_on_host():
+    _abi, lib = _lib()
+    from synth import nodes
+    xyz, flags, h = nodes.jittered_grid((11, 11), seed=1)
+    xyz = np.ascontiguousarray(xyz)
+    plan = C.c_void_p()
+    ok = _params(_abi)
+    rc = lib.rbffd_plan_create(C.byref(ok), xyz.shape[0], xyz.ctypes.data, flags.ctypes.data, 0, None, None,
+                               C.byref(plan))
+    assert rc == 0
+    s = _abi.Sizes()
+    assert lib.rbffd_plan_sizes(plan, C.byref(s)) == 0
+    assert s.N == 121 and s.n_stencil == 31 and s.n_hv == 31 and s.fe == 1 and s.fh == 2
+    assert abs(s.dt - 0.1 / (10 * np.sqrt(2))) < 1e-18
+    assert abs(s.gamma - (-1.0 * 0.1 ** 4)) < 1e-20          # c (-1)^(alpha-1) h^(2 alpha)
+    assert s.arena_bytes > 0 and s.e_bytes == 121 * 8
+    # out-of-order use is refused without touching the device
+    assert lib.rbffd_get_perm(plan, 0, np.zeros(121, np.int32).ctypes.data, None) == _abi.ESTATE
+    lib.rbffd_plan_destroy(plan)
+    # n must exceed M_m; stencils must fit; BF16 needs F32 weights
+    for bad in (dict(n=6), dict(n=200), dict(fdtype=2, wdtype=0), dict(dim=4), dict(phs_k=4)):
+        p = _params(_abi, **bad)
+        rc = lib.rbffd_plan_create(C.byref(p), xyz.shape[0], xyz.ctypes.data, flags.ctypes.data, 0, None, None,
+                                   C.byref(plan))
+        assert rc in (_abi.EINVAL, _abi.ESIZE, _abi.ENOTSUP), bad
+    assert lib.rbffd_strerror(_abi.ESINGULAR) == b"singular local weight system"

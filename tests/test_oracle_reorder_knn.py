@@ -7,7 +7,7 @@ from oracle import reorder, knn
 def test_morton_hand_examples_2d():
     s = 2.0 ** -32
     xyz = np.array([[0, 0], [s, 0], [0, s], [s, s], [2 * s, 0], [0, 2 * s], [3 * s, 3 * s]])
-    k = reorder.morton_keys(xyz, (0, 0), (1, 1))
+    k = reorder.morton_keys(xyz, (0, 0), 1.0)
     # bit i of qx -> key bit 2i, bit i of qy -> key bit 2i+1
     assert k.tolist() == [0, 1, 2, 3, 4, 8, 15]
 
@@ -15,15 +15,23 @@ def test_morton_hand_examples_2d():
 def test_morton_hand_examples_3d_and_clamp():
     s = 2.0 ** -21
     xyz = np.array([[s, 0, 0], [0, s, 0], [0, 0, s], [2 * s, 0, 0], [1.0, 1.0, 1.0]])
-    k = reorder.morton_keys(xyz, (0, 0, 0), (1, 1, 1))
+    k = reorder.morton_keys(xyz, (0, 0, 0), 1.0)
     assert k[:4].tolist() == [1, 2, 4, 8]
     assert int(k[4]) == (1 << 63) - 1          # q = 2^21 clamps to 2^21 - 1
 
 
 def test_morton_order_is_stable_on_ties():
     xyz = np.array([[0.5, 0.5], [0.1, 0.1], [0.5, 0.5], [0.1, 0.1]])
-    p = reorder.morton_order(xyz, (0, 0), (1, 1))
+    p = reorder.morton_order(xyz, (0, 0), 1.0)
     assert p.tolist() == [1, 3, 0, 2]
+
+
+def test_morton_box_is_square():
+    lo, side = reorder.morton_box((0.0, 0.0), (200.0, 20.0))
+    assert lo == (0.0, 0.0) and side == 200.0
+    s = 200.0 * 2.0 ** -32
+    k = reorder.morton_keys(np.array([[0.0, s], [s, 0.0]]), lo, side)
+    assert k.tolist() == [2, 1]
 
 
 def test_rcm_hand_example_path():
