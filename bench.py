@@ -119,12 +119,19 @@ def main():
     t_gen = time.time() - t0
     log(f"workload: N={w.N} h={w.h:.3e} n={w.n} m={w.m} alpha={w.alpha} n_hv={w.n_hv} (generated in {t_gen:.1f} s)")
 
-    def setup(prec):
+    def setup_w(wl, prec):
         torch.cuda.synchronize()
         t = time.time()
-        s = Solver.from_workload(w, precision=prec)
+        s = Solver.from_workload(wl, precision=prec)
         torch.cuda.synchronize()
         return s, time.time() - t
+
+    def setup(prec):
+        return setup_w(w, prec)
+
+    def rl2(x, y):
+        ny = np.linalg.norm(y)
+        return float(np.linalg.norm(x - y) / ny) if ny > 0 and np.isfinite(ny) else float("nan")
 
     s, t_setup = setup(args.precision)
     st = s.state(w.E0, w.H0)
@@ -197,10 +204,6 @@ def main():
         E32, E64 = s.E_original(a32), s64.E_original(a64)
         H32, H64 = s.H_original(a32), s64.H_original(a64)
 
-        def rl2(x, y):
-            ny = np.linalg.norm(y)
-            return float(np.linalg.norm(x - y) / ny) if ny > 0 and np.isfinite(ny) else float("nan")
-
         u64 = r64["energy"] / r64["energy"][0]
         extras["accuracy"] = {
             "steps": T, "reference": "GPU FP64 path (pinned to the FP64 oracle at 1e-12 on smaller cases)",
@@ -227,6 +230,58 @@ def main():
                              "alg_bytes_per_field_node_step": 50.0,
                              "hbm_frac_at_50B": round(wb.N * 64 * kb / tb * 50.0 / (HBM_PEAK_GBS * 1e9), 4)}
         log(f"batched: {extras['batched']}")
+        del sb, stb
+        torch.cuda.empty_cache()
+        # the same nodes and stencils with alpha = 2 (c*dt = 1e-3), which is
+        # stable: FP32 vs FP64 after 10^4 steps
+        ws = configs.Workload(w.name, w.dim, w.xyz, w.flags, w.h, w.n, w.m, 2, 31, 1e-3, T)
+        ws.E0, ws.H0 = w.E0, w.H0
+        acc = {}
+        for prec in ("f32", "f64"):
+            sv = Solver.from_workload(ws, precision=prec)
+            sa = sv.state(ws.E0, ws.H0)
+            r = sv.run(sa, T, energy_every=max(1, T // 20), use_graph=True)
+            acc[prec] = (sv.E_original(sa), sv.H_original(sa), r["energy"])
+            del sv, sa
+            torch.cuda.empty_cache()
+        u = acc["f64"][2] / acc["f64"][2][0]
+        extras["accuracy_alpha2"] = {
+            "steps": T, "alpha": 2, "n_hv": 31, "chat": 1e-3,
+            "fp32_vs_fp64_rel_l2_E": rl2(acc["f32"][0], acc["f64"][0]),
+            "fp32_vs_fp64_rel_l2_H": rl2(acc["f32"][1], acc["f64"][1]),
+            "fp64_energy_ratio_min": float(u.min()), "fp64_energy_ratio_max": float(u.max())}
+        log(f"accuracy (alpha=2 variant): {extras['accuracy_alpha2']}")
+        # 3D cube, 8.0M nodes, FP32 rate and FP32 vs FP64 over the workload's 2000 steps
+        w3 = configs.tm111_3d(scale=1.0, chat=1e-3)
+        r3 = {}
+        for prec in ("f32", "f64"):
+            s3, t3 = setup_w(w3, prec)
+            a3 = s3.state(w3.E0, w3.H0)
+            s3.run(a3, 10, use_graph=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            s3.run(a3, 200, use_graph=True)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rate = w3.N * 200 / (e0.elapsed_time(e1) * 1e-3)
+            th3, te3 = time_halves(s3, a3, 10, torch)
+            a3 = s3.state(w3.E0, w3.H0)
+            s3.run(a3, w3.steps, use_graph=True)
+            r3[prec] = dict(rate=rate, setup=t3, th=th3, te=te3, E=s3.E_original(a3), H=s3.H_original(a3))
+            del s3, a3
+            torch.cuda.empty_cache()
+        sw3 = 4
+        bh3 = alg_bytes_half(w3.n, w3.n_hv, 3, sw3, 4, 3, 3, 0) * w3.N
+        extras["tm111_3d"] = {
+            "N": w3.N, "n": w3.n, "n_hv": w3.n_hv, "value_f32": r3["f32"]["rate"], "value_f64": r3["f64"]["rate"],
+            "unit": "node-steps/s", "setup_s_f32": round(r3["f32"]["setup"], 2),
+            "h_update_us": round(r3["f32"]["th"] * 1e6, 1), "e_update_us": round(r3["f32"]["te"] * 1e6, 1),
+            "h_update_GBs": round(bh3 / r3["f32"]["th"] / 1e9, 1),
+            "h_update_frac": round(bh3 / r3["f32"]["th"] / 1e9 / HBM_PEAK_GBS, 4),
+            "steps_accuracy": w3.steps,
+            "fp32_vs_fp64_rel_l2_E": rl2(r3["f32"]["E"], r3["f64"]["E"]),
+            "fp32_vs_fp64_rel_l2_H": rl2(r3["f32"]["H"], r3["f64"]["H"])}
+        log(f"3D: {extras['tm111_3d']}")
 
     cpu = None
     if not args.no_cpu_baseline:

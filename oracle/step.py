@@ -53,40 +53,47 @@ def pec_keep(flags, dim):
     return keep
 
 
-def h_update(E, H, op, a, gamma):
-    """H^{n+1} from E^n and H^n (first lines of eq. 19)."""
+def h_update(E, H, op, a, gamma, rows=None):
+    """H^{n+1} from E^n and H^n (first lines of eq. 19).
+
+    ``rows`` (default: every node) names the centres the operator rows belong
+    to, so that a subset of nodes can be updated on its own.
+    """
     cw, ci = op["curl_w"], op["curl_idx"]
     hw, hi = op["hv_w"], op["hv_idx"]
+    Hc = H if rows is None else H[rows]
     if H.shape[1] == 2:
         Ez = E[:, 0]
-        Hx = H[:, 0] - a * (D(cw[:, 1], ci, Ez) - gamma * D(hw, hi, H[:, 0]))
-        Hy = H[:, 1] + a * (D(cw[:, 0], ci, Ez) + gamma * D(hw, hi, H[:, 1]))
+        Hx = Hc[:, 0] - a * (D(cw[:, 1], ci, Ez) - gamma * D(hw, hi, H[:, 0]))
+        Hy = Hc[:, 1] + a * (D(cw[:, 0], ci, Ez) + gamma * D(hw, hi, H[:, 1]))
         return np.stack([Hx, Hy], axis=1)
     dx = lambda f: D(cw[:, 0], ci, f)
     dy = lambda f: D(cw[:, 1], ci, f)
     dz = lambda f: D(cw[:, 2], ci, f)
     Ex, Ey, Ez = E[:, 0], E[:, 1], E[:, 2]
     curl = [dy(Ez) - dz(Ey), dz(Ex) - dx(Ez), dx(Ey) - dy(Ex)]
-    return np.stack([H[:, c] - a * (curl[c] - gamma * D(hw, hi, H[:, c])) for c in range(3)], axis=1)
+    return np.stack([Hc[:, c] - a * (curl[c] - gamma * D(hw, hi, H[:, c])) for c in range(3)], axis=1)
 
 
-def e_update(E, Hn, op, kappa, gamma, keep, src=None):
+def e_update(E, Hn, op, kappa, gamma, keep, src=None, rows=None):
     """E^{n+1} from E^n and H^{n+1} (last line of eq. 19), then PEC.
 
     src = (nodes [S], values [S]) adds values at nodes after the bracket.
+    ``rows`` as in h_update (keep and an array kappa are then per row).
     """
     cw, ci = op["curl_w"], op["curl_idx"]
     hw, hi = op["hv_w"], op["hv_idx"]
+    Ec = E if rows is None else E[rows]
     if Hn.shape[1] == 2:
         br = D(cw[:, 0], ci, Hn[:, 1]) - D(cw[:, 1], ci, Hn[:, 0]) + gamma * D(hw, hi, E[:, 0])
-        out = (E[:, 0] + kappa * br)[:, None]
+        out = (Ec[:, 0] + kappa * br)[:, None]
     else:
         dx = lambda f: D(cw[:, 0], ci, f)
         dy = lambda f: D(cw[:, 1], ci, f)
         dz = lambda f: D(cw[:, 2], ci, f)
         Hx, Hy, Hz = Hn[:, 0], Hn[:, 1], Hn[:, 2]
         curl = [dy(Hz) - dz(Hy), dz(Hx) - dx(Hz), dx(Hy) - dy(Hx)]
-        out = np.stack([E[:, c] + kappa * (curl[c] + gamma * D(hw, hi, E[:, c])) for c in range(3)], axis=1)
+        out = np.stack([Ec[:, c] + kappa * (curl[c] + gamma * D(hw, hi, E[:, c])) for c in range(3)], axis=1)
     if src is not None:
         nodes, vals = src
         for s in range(len(nodes)):

@@ -49,6 +49,7 @@ struct OpBlock {
     int64_t* t_off = nullptr;      // [tiles + 1] start of each tile's entries
     int32_t* t_width = nullptr;    // [tiles]
     int32_t* t_src = nullptr;      // [entries]  source row i
+    int32_t* t_slot = nullptr;     // [entries]  slot s of row i (-1 = padding)
     void* t_w = nullptr;           // [entries][4] (wx, wy, wh, 0) in weight precision
     int64_t t_cap = 0;             // entry capacity
 };
@@ -86,6 +87,7 @@ struct rbffd_plan {
     bool collocated = true;
     // arena / workspace bookkeeping
     int64_t arena_bytes = 0, ws_bytes = 0, adj_ws_bytes = 0;
+    int64_t t_entries = 0;       // entries of the transposed operator
     char* arena = nullptr;
     bool ready = false;
     Variant var;
@@ -127,6 +129,7 @@ int setup_nodes_and_stencils(rbffd_plan* p, void* ws, hipStream_t s);
 int setup_weights(rbffd_plan* p, void* ws, hipStream_t s);
 int pack_all(rbffd_plan* p, void* ws, hipStream_t s);
 int build_transpose(rbffd_plan* p, void* ws, hipStream_t s);
+int refill_transpose(rbffd_plan* p, hipStream_t s);
 int64_t setup_ws_bytes(const rbffd_plan* p);
 int capture_stream(const rbffd_plan* p, hipStream_t* out);
 

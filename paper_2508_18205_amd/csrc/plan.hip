@@ -113,6 +113,7 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int K, bool adjoint) {
         // size (6 in 2D); the SELL rows are padded to their tile's maximum.
         o.t_cap = T * 6 * (int64_t)o.ns;
         o.t_src = b.take<int32_t>(o.t_cap);
+        o.t_slot = b.take<int32_t>(o.t_cap);
         o.t_w = b.take_bytes(o.t_cap * 4 * wb);
     }
 }
@@ -370,12 +371,7 @@ extern "C" int rbffd_set_weights(rbffd_plan* p, int32_t op, const double* in, vo
     HIPCHK(p, hipMemcpyAsync(dst, in, count * 8, hipMemcpyHostToDevice, s));
     rc = pack_all(p, nullptr, s);
     if (rc) return rc;
-    if (p->p.adjoint) {
-        // the transposed operator is rebuilt from the new weights; it needs
-        // scratch, which the caller gave to rbffd_weights -- not kept, so the
-        // adjoint of injected weights is not supported
-        return set_err(p, RBFFD_ENOTSUP, "set_weights on an adjoint plan: rebuild the plan instead");
-    }
+    if (p->p.adjoint && (rc = refill_transpose(p, s))) return rc;
     HIPCHK(p, hipStreamSynchronize(s));
     return RBFFD_OK;
 }

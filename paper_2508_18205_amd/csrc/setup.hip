@@ -591,10 +591,10 @@ __global__ void k_twidth(const int32_t* rstart, const int32_t* rend, int64_t N, 
     width[t] = w;
 }
 
-template <typename TW>
+// SELL layout of D^T: entry (tile t, column q, lane l) = the q-th incoming
+// entry of row j = 64 t + l; records the source row i and the slot s
 __global__ void k_tfill(const uint64_t* skeys, const int32_t* rstart, const int32_t* rend, const int64_t* toff,
-                        const int32_t* width, const double* wc, const double* wh, int64_t N, int ns, int n, int nh,
-                        int64_t tiles, int32_t* tsrc, TW* tw) {
+                        const int32_t* width, int64_t N, int ns, int64_t tiles, int32_t* tsrc, int32_t* tslot) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= tiles * RBFFD_TILE) return;
     const int64_t t = g / RBFFD_TILE;
@@ -608,18 +608,27 @@ __global__ void k_tfill(const uint64_t* skeys, const int32_t* rstart, const int3
         if (q < deg) {
             const uint64_t key = skeys[rstart[j] + q];
             const int64_t rem = (int64_t)(key % (uint64_t)(N * ns));
-            const int64_t i = rem / ns;
-            const int s = (int)(rem % ns);
-            tsrc[e] = (int32_t)i;
-            tw[e * 4 + 0] = (TW)(s < n ? wc[(i * 2 + 0) * n + s] : 0.0);
-            tw[e * 4 + 1] = (TW)(s < n ? wc[(i * 2 + 1) * n + s] : 0.0);
-            tw[e * 4 + 2] = (TW)(s < nh ? wh[i * nh + s] : 0.0);
-            tw[e * 4 + 3] = (TW)0.0;
+            tsrc[e] = (int32_t)(rem / ns);
+            tslot[e] = (int32_t)(rem % ns);
         } else {
             tsrc[e] = (int32_t)jc;
-            for (int c = 0; c < 4; ++c) tw[e * 4 + c] = (TW)0.0;
+            tslot[e] = -1;
         }
     }
+}
+
+// transposed weights (wx, wy, wh, 0) of every SELL entry from the FP64 weights
+template <typename TW>
+__global__ void k_tweights(const int32_t* tsrc, const int32_t* tslot, int64_t E, const double* wc, const double* wh,
+                           int n, int nh, TW* tw) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const int s = tslot[e];
+    const int64_t i = tsrc[e];
+    tw[e * 4 + 0] = (TW)((s >= 0 && s < n) ? wc[(i * 2 + 0) * n + s] : 0.0);
+    tw[e * 4 + 1] = (TW)((s >= 0 && s < n) ? wc[(i * 2 + 1) * n + s] : 0.0);
+    tw[e * 4 + 2] = (TW)((s >= 0 && s < nh) ? wh[i * nh + s] : 0.0);
+    tw[e * 4 + 3] = (TW)0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1076,14 +1085,28 @@ int build_transpose(rbffd_plan* p, void* wsp, hipStream_t st) {
     if (off[o.tiles] > o.t_cap) return set_err(p, RBFFD_ESIZE, "transposed operator exceeds its capacity");
     HIPCHK(p, hipMemcpyAsync(o.t_off, off.data(), (o.tiles + 1) * 8, hipMemcpyHostToDevice, st));
     const int64_t G = o.tiles * RBFFD_TILE;
-    if (p->p.wdtype == RBFFD_F64)
-        hipLaunchKernelGGL(k_tfill<double>, dim3(blocks(G)), dim3(256), 0, st, kout, rstart, rend, o.t_off, o.t_width,
-                           o.wc, o.wh, N, (int)ns, o.n, o.nh, o.tiles, o.t_src, (double*)o.t_w);
-    else
-        hipLaunchKernelGGL(k_tfill<float>, dim3(blocks(G)), dim3(256), 0, st, kout, rstart, rend, o.t_off, o.t_width,
-                           o.wc, o.wh, N, (int)ns, o.n, o.nh, o.tiles, o.t_src, (float*)o.t_w);
+    hipLaunchKernelGGL(k_tfill, dim3(blocks(G)), dim3(256), 0, st, kout, rstart, rend, o.t_off, o.t_width, N, (int)ns,
+                       o.tiles, o.t_src, o.t_slot);
+    p->t_entries = off[o.tiles];
+    int rc = refill_transpose(p, st);
+    if (rc) return rc;
     HIPCHK(p, hipGetLastError());
     HIPCHK(p, hipStreamSynchronize(st));
+    p->opE = p->opH;
+    return RBFFD_OK;
+}
+
+int refill_transpose(rbffd_plan* p, hipStream_t st) {
+    OpBlock& o = p->opH;
+    const int64_t E = p->t_entries;
+    if (E <= 0) return RBFFD_OK;
+    if (p->p.wdtype == RBFFD_F64)
+        hipLaunchKernelGGL(k_tweights<double>, dim3(blocks(E)), dim3(256), 0, st, o.t_src, o.t_slot, E, o.wc, o.wh,
+                           o.n, o.nh, (double*)o.t_w);
+    else
+        hipLaunchKernelGGL(k_tweights<float>, dim3(blocks(E)), dim3(256), 0, st, o.t_src, o.t_slot, E, o.wc, o.wh,
+                           o.n, o.nh, (float*)o.t_w);
+    HIPCHK(p, hipGetLastError());
     p->opE = p->opH;
     return RBFFD_OK;
 }

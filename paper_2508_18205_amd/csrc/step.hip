@@ -775,7 +775,9 @@ void full_step(const rbffd_plan* p, const rbffd_fields* f, int c, const rbffd_ru
                                    a->n_rcv, a->rcv_node, a->traces, w.ctr, a->T);
         }
     }
-    hipLaunchKernelGGL(k_ctr_inc, dim3(1), dim3(64), 0, st, w.ctr);
+    // the step counter only feeds the auxiliary kernels
+    if (a->ckpt || a->n_src > 0 || a->n_rcv > 0 || (a->energy_out && a->energy_every > 0))
+        hipLaunchKernelGGL(k_ctr_inc, dim3(1), dim3(64), 0, st, w.ctr);
 }
 }  // namespace
 
