@@ -232,9 +232,9 @@ def main():
         log(f"batched: {extras['batched']}")
         del sb, stb
         torch.cuda.empty_cache()
-        # the same nodes and stencils with alpha = 2 (c*dt = 1e-3), which is
-        # stable: FP32 vs FP64 after 10^4 steps
-        ws = configs.Workload(w.name, w.dim, w.xyz, w.flags, w.h, w.n, w.m, 2, 31, 1e-3, T)
+        # the same nodes and curl stencils with alpha = 2 (c*dt = 3e-3), which is
+        # stable at this size: FP32 vs FP64 after 10^4 steps
+        ws = configs.Workload(w.name, w.dim, w.xyz, w.flags, w.h, w.n, w.m, 2, 31, 3e-3, T)
         ws.E0, ws.H0 = w.E0, w.H0
         acc = {}
         for prec in ("f32", "f64"):
@@ -246,7 +246,7 @@ def main():
             torch.cuda.empty_cache()
         u = acc["f64"][2] / acc["f64"][2][0]
         extras["accuracy_alpha2"] = {
-            "steps": T, "alpha": 2, "n_hv": 31, "chat": 1e-3,
+            "steps": T, "alpha": 2, "n_hv": 31, "chat": 3e-3,
             "fp32_vs_fp64_rel_l2_E": rl2(acc["f32"][0], acc["f64"][0]),
             "fp32_vs_fp64_rel_l2_H": rl2(acc["f32"][1], acc["f64"][1]),
             "fp64_energy_ratio_min": float(u.min()), "fp64_energy_ratio_max": float(u.max())}
