@@ -11,6 +11,8 @@
 #define RBFFD_MAX_STENCIL 128     // max(n, n_hv) supported
 #define RBFFD_MAX_MONO 64         // monomials per local system
 #define RBFFD_TILE 64             // nodes per packed tile (one wavefront)
+#define RBFFD_WGT 256             // nodes per LDS-staged workgroup tile (4 wavefronts)
+#define RBFFD_LDS_BUDGET 65536    // bytes of LDS one staged workgroup may use
 
 // ---------------------------------------------------------------------------
 // Device-side layout of one operator block (the weights applied in one half
@@ -45,6 +47,15 @@ struct OpBlock {
     int32_t* bidx = nullptr;       // [Nt][S4*4]
     float* bwc = nullptr;          // [Nt][dim][C4*4]
     float* bwh = nullptr;          // [Nt][V4*4]
+    // LDS staging (collocated): per 256-node workgroup tile, the sorted unique
+    // source nodes of all its stencils ("halo list") and, per node and slot,
+    // the 16-bit position of the slot's node in that list
+    uint16_t* lidx = nullptr;      // [tiles][Q8][64][8]
+    int32_t* hpool = nullptr;      // concatenated halo lists
+    int32_t* hoff = nullptr;       // [nwg + 1] start of each workgroup's list
+    int32_t Q8 = 0;
+    int64_t nwg = 0;
+    int32_t hmax = 0;              // longest halo list (0 = staging unavailable)
     // transposed operator for the adjoint (collocated 2D)
     int64_t* t_off = nullptr;      // [tiles + 1] start of each tile's entries
     int32_t* t_width = nullptr;    // [tiles]
@@ -71,6 +82,7 @@ struct Variant {
     int block = 256;      // threads per workgroup (multiple of 64)
     int xcd = 1;          // XCD-aware block remap
     int persist = 8;      // K-field batch: resident workgroups per CU
+    int lds = 1;          // use the LDS-staged step kernels when available
 };
 
 struct rbffd_plan {
@@ -130,6 +142,7 @@ int setup_weights(rbffd_plan* p, void* ws, hipStream_t s);
 int pack_all(rbffd_plan* p, void* ws, hipStream_t s);
 int build_transpose(rbffd_plan* p, void* ws, hipStream_t s);
 int refill_transpose(rbffd_plan* p, hipStream_t s);
+int build_halos(rbffd_plan* p, void* ws, hipStream_t s);
 int64_t setup_ws_bytes(const rbffd_plan* p);
 int capture_stream(const rbffd_plan* p, hipStream_t* out);
 

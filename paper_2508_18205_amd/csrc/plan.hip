@@ -90,6 +90,13 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int K, bool adjoint) {
     if (!o.cross) {
         o.st_union = b.take<int32_t>(o.Nt * o.ns);
         o.pidx = b.take_bytes(T * o.S4 * 16);
+        if (K == 1) {
+            o.Q8 = (int)cdiv(o.ns - 1, 8);
+            o.nwg = cdiv(o.tiles, RBFFD_WGT / RBFFD_TILE);
+            o.lidx = b.take<uint16_t>(T * o.Q8 * 8);
+            o.hpool = b.take<int32_t>(o.Nt * o.ns);
+            o.hoff = b.take<int32_t>(o.nwg + 1);
+        }
     } else {
         o.st_curl = b.take<int32_t>(o.Nt * o.n);
         o.st_hv = o.nh > 0 ? b.take<int32_t>(o.Nt * o.nh) : nullptr;
@@ -378,6 +385,17 @@ extern "C" int rbffd_set_weights(rbffd_plan* p, int32_t op, const double* in, vo
 
 extern "C" int rbffd_get_variant(const rbffd_plan* p, int32_t* v) {
     if (!p || !v) return RBFFD_EINVAL;
-    *v = p->var.block | (p->var.xcd << 16);
+    *v = p->var.block | (p->var.xcd << 16) | (p->var.lds << 17) | (p->var.persist << 20);
+    return RBFFD_OK;
+}
+
+extern "C" int rbffd_set_variant(rbffd_plan* p, int32_t block, int32_t xcd, int32_t lds, int32_t persist) {
+    if (!p) return RBFFD_EINVAL;
+    if (block < 64 || block > 512 || (block % 64) || persist < 1 || persist > 64)
+        return set_err(p, RBFFD_EINVAL, "bad launch variant");
+    p->var.block = block;
+    p->var.xcd = xcd ? 1 : 0;
+    p->var.lds = lds ? 1 : 0;
+    p->var.persist = persist;
     return RBFFD_OK;
 }

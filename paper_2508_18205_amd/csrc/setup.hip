@@ -632,6 +632,65 @@ __global__ void k_tweights(const int32_t* tsrc, const int32_t* tslot, int64_t E,
 }
 
 // ---------------------------------------------------------------------------
+// Halo lists for LDS staging: per 256-node workgroup tile the sorted unique
+// source nodes of its stencils, and per (node, slot) the 16-bit position of
+// the slot's node in that list.  Built from one global sort of
+// (tile, source) keys.
+// ---------------------------------------------------------------------------
+__global__ void k_hkeys(const int32_t* st, int64_t N, int ns, uint64_t* keys) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= N * ns) return;
+    const int64_t i = e / ns;
+    keys[e] = ((uint64_t)(i / RBFFD_WGT) << 32) | (uint64_t)(uint32_t)st[e];
+}
+
+__global__ void k_hflags(const uint64_t* sk, int64_t E, int32_t* flag) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < E) flag[e] = (e == 0 || sk[e] != sk[e - 1]) ? 1 : 0;
+}
+
+__global__ void k_hcompact(const uint64_t* sk, const int32_t* flag, const int32_t* pos, int64_t E, int32_t* pool,
+                           int32_t* hoff, int64_t nwg) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    if (flag[e]) {
+        pool[pos[e]] = (int32_t)(sk[e] & 0xFFFFFFFFull);
+        const uint64_t t = sk[e] >> 32;
+        if (e == 0 || (sk[e - 1] >> 32) != t) hoff[t] = pos[e];
+    }
+    if (e == E - 1) hoff[nwg] = pos[e] + flag[e];
+}
+
+__device__ __forceinline__ int lower_pos(const int32_t* a, int n, int32_t v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_hlocal(const int32_t* st, int64_t N, int ns, const int32_t* pool, const int32_t* hoff, int Q8,
+                         int64_t tiles, uint16_t* lidx) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= tiles * RBFFD_TILE) return;
+    const int64_t tile = g / RBFFD_TILE;
+    const int lane = (int)(g % RBFFD_TILE);
+    const bool real = g < N;
+    const int64_t wg = g / RBFFD_WGT;
+    const int32_t* L = pool + hoff[wg];
+    const int cnt = hoff[wg + 1] - hoff[wg];
+    const int self = real ? lower_pos(L, cnt, (int32_t)g) : 0;
+    for (int q = 0; q < Q8; ++q)
+        for (int u = 0; u < 8; ++u) {
+            const int s = 1 + 8 * q + u;
+            const int pos = (real && s < ns) ? lower_pos(L, cnt, st[g * ns + s]) : self;
+            lidx[((tile * Q8 + q) * RBFFD_TILE + lane) * 8 + u] = (uint16_t)pos;
+        }
+}
+
+// ---------------------------------------------------------------------------
 // workspace bump allocator
 // ---------------------------------------------------------------------------
 struct WS {
@@ -664,6 +723,13 @@ size_t sort_temp_bytes(int64_t N) {
     if (hipcub::DeviceRadixSort::SortPairs(nullptr, t, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
                                            (int32_t*)nullptr, (int)N, 0, 64) != hipSuccess)
         t = (size_t)N * 24 + (1u << 22);
+    return t;
+}
+
+size_t scan_temp_bytes(int64_t E) {
+    size_t t = 0;
+    if (hipcub::DeviceScan::ExclusiveSum(nullptr, t, (int32_t*)nullptr, (int32_t*)nullptr, (int)E) != hipSuccess)
+        t = (size_t)E / 64 + (1u << 22);
     return t;
 }
 
@@ -829,6 +895,17 @@ int64_t setup_ws_bytes(const rbffd_plan* p) {
     }
     w.take<int32_t>(64);   // status
     int64_t need = w.off;
+    if (p->collocated && p->K == 1) {
+        WS t{nullptr};
+        const int64_t E = p->E.N * p->ns;
+        t.take<uint64_t>(E);
+        t.take<uint64_t>(E);
+        t.take<int32_t>(E);
+        t.take<int32_t>(E);
+        t.take<char>((int64_t)key_sort_temp_bytes(E));
+        t.take<char>((int64_t)scan_temp_bytes(E));
+        need = std::max(need, t.off);
+    }
     if (p->p.adjoint) {
         WS t{nullptr};
         const int64_t E = p->E.N * p->ns;
@@ -1096,6 +1173,43 @@ int build_transpose(rbffd_plan* p, void* wsp, hipStream_t st) {
     return RBFFD_OK;
 }
 
+int build_halos(rbffd_plan* p, void* wsp, hipStream_t st) {
+    OpBlock& o = p->opH;
+    o.hmax = 0;
+    if (!o.lidx) return RBFFD_OK;
+    const int64_t N = o.Nt, ns = o.ns, E = N * ns;
+    if (E > INT32_MAX) return RBFFD_OK;   // too many entries for the 32-bit scan: no staging
+    WS w{(char*)wsp};
+    uint64_t* kin = w.take<uint64_t>(E);
+    uint64_t* kout = w.take<uint64_t>(E);
+    int32_t* flag = w.take<int32_t>(E);
+    int32_t* pos = w.take<int32_t>(E);
+    size_t tb = key_sort_temp_bytes(E), sb = scan_temp_bytes(E);
+    void* temp = w.take<char>((int64_t)tb);
+    void* stemp = w.take<char>((int64_t)sb);
+    hipLaunchKernelGGL(k_hkeys, dim3(blocks(E)), dim3(256), 0, st, o.st_union, N, (int)ns, kin);
+    int end_bit = 32;
+    while (end_bit < 64 && ((uint64_t)1 << (end_bit - 32)) <= (uint64_t)o.nwg) ++end_bit;
+    HIPCHK(p, hipcub::DeviceRadixSort::SortKeys(temp, tb, kin, kout, (int)E, 0, end_bit, st));
+    hipLaunchKernelGGL(k_hflags, dim3(blocks(E)), dim3(256), 0, st, kout, E, flag);
+    HIPCHK(p, hipcub::DeviceScan::ExclusiveSum(stemp, sb, flag, pos, (int)E, st));
+    hipLaunchKernelGGL(k_hcompact, dim3(blocks(E)), dim3(256), 0, st, kout, flag, pos, E, o.hpool, o.hoff, o.nwg);
+    hipLaunchKernelGGL(k_hlocal, dim3(blocks(o.tiles * RBFFD_TILE)), dim3(256), 0, st, o.st_union, N, (int)ns, o.hpool,
+                       o.hoff, o.Q8, o.tiles, o.lidx);
+    HIPCHK(p, hipGetLastError());
+    std::vector<int32_t> off(o.nwg + 1);
+    HIPCHK(p, hipMemcpyAsync(off.data(), o.hoff, (o.nwg + 1) * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+    int32_t mx = 0;
+    for (int64_t t = 0; t < o.nwg; ++t) mx = std::max(mx, off[t + 1] - off[t]);
+    // staging only when a workgroup's list fits the LDS budget and 16-bit positions
+    const int fb = field_elem_bytes(p->p.fdtype) == 8 ? 8 : 4;
+    const int64_t per = (int64_t)(p->FE + p->FH) * fb;
+    o.hmax = (mx < 65536 && (int64_t)mx * per <= RBFFD_LDS_BUDGET) ? mx : 0;
+    p->opE = p->opH;
+    return RBFFD_OK;
+}
+
 int refill_transpose(rbffd_plan* p, hipStream_t st) {
     OpBlock& o = p->opH;
     const int64_t E = p->t_entries;
@@ -1125,6 +1239,7 @@ extern "C" int rbffd_weights(rbffd_plan* p, void* arena, void* ws, void* stream)
     if (rc) return rc;
     if ((rc = setup_weights(p, ws, st))) return rc;
     if ((rc = pack_all(p, ws, st))) return rc;
+    if (p->collocated && p->K == 1 && (rc = build_halos(p, ws, st))) return rc;
     if (p->p.adjoint && (rc = build_transpose(p, ws, st))) return rc;
     HIPCHK(p, hipStreamSynchronize(st));
     p->ready = true;

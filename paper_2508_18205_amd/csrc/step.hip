@@ -43,6 +43,11 @@ struct SA {
     double dt, eps0;
     const void* eps_r;    // per-node eps_r (double for FP64 fields, else float) or null
     const uint8_t* emask;
+    // LDS staging
+    const uint4* lidx;    // [tiles][Q8][64] x 8 u16 halo positions
+    const int32_t* hpool;
+    const int32_t* hoff;
+    int Q8, hmax;
 };
 
 template <typename TS, typename TW>
@@ -437,6 +442,292 @@ __global__ __launch_bounds__(512) void k_e3(SA<TS, TW> a) {
     }
 }
 
+// ---- LDS-staged variants ------------------------------------------------------
+// A workgroup owns 256 consecutive nodes (4 wavefront tiles).  It first copies
+// the field values of every node its stencils touch (the sorted halo list)
+// into LDS with one coalesced pass, then each node sums over its slots with
+// 16-bit halo positions (8 per 16-byte load) instead of 32-bit global indices
+// and global gathers.  Same arithmetic and summation order as the global
+// variants.
+__device__ __forceinline__ int pos4(const uint4& v, int half, int u) {
+    const uint32_t w = half ? (u < 2 ? v.z : v.w) : (u < 2 ? v.x : v.y);
+    return (int)((u & 1) ? (w >> 16) : (w & 0xFFFFu));
+}
+
+template <typename TC>
+__device__ __forceinline__ TC* lds_base() {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    return reinterpret_cast<TC*>(smem_raw);
+}
+
+template <typename TS, typename TW>
+__global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    TC* sE = lds_base<TC>();
+    TC* sH = sE + ((a.hmax + 3) & ~3);                 // pairs (Hx, Hy)
+    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
+    for (int k = threadIdx.x; k < hc; k += blockDim.x) {
+        const int j = a.hpool[h0 + k];
+        sE[k] = S::ld1(a.E, j);
+        S::ld2(a.H, j, sH[2 * k], sH[2 * k + 1]);
+    }
+    __syncthreads();
+    const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
+    if (tile >= a.tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    const TC e0 = S::ld1(a.E, ic);
+    TC hx0, hy0;
+    S::ld2(a.H, ic, hx0, hy0);
+    TC dx = 0, dy = 0, vx = 0, vy = 0;
+    const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const int qb = min(a.C4, a.V4), qm = max(a.C4, a.V4);
+    uint4 li = make_uint4(0, 0, 0, 0);
+    for (int q = 0; q < qm; ++q) {
+        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
+        const int hf = q & 1;
+        if (q < qb) {
+            TW wx[4], wy[4], wh[4];
+            ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+            ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+            ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = pos4(li, hf, u);
+                const TC de = sE[k] - e0;
+                dx += (TC)wx[u] * de;
+                dy += (TC)wy[u] * de;
+                vx += (TC)wh[u] * (sH[2 * k] - hx0);
+                vy += (TC)wh[u] * (sH[2 * k + 1] - hy0);
+            }
+        } else if (q < a.C4) {
+            TW wx[4], wy[4];
+            ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+            ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const TC de = sE[pos4(li, hf, u)] - e0;
+                dx += (TC)wx[u] * de;
+                dy += (TC)wy[u] * de;
+            }
+        } else {
+            TW wh[4];
+            ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = pos4(li, hf, u);
+                vx += (TC)wh[u] * (sH[2 * k] - hx0);
+                vy += (TC)wh[u] * (sH[2 * k + 1] - hy0);
+            }
+        }
+    }
+    if (i < a.N) {
+        const TC A = (TC)a.a, G = (TC)a.g;
+        S::st2(a.out, i, hx0 + A * (-dy + G * vx), hy0 + A * (dx + G * vy));
+    }
+}
+
+template <typename TS, typename TW>
+__global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    TC* sE = lds_base<TC>();
+    TC* sH = sE + ((a.hmax + 3) & ~3);
+    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
+    for (int k = threadIdx.x; k < hc; k += blockDim.x) {
+        const int j = a.hpool[h0 + k];
+        sE[k] = S::ld1(a.E, j);
+        S::ld2(a.H, j, sH[2 * k], sH[2 * k + 1]);
+    }
+    __syncthreads();
+    const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
+    if (tile >= a.tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    const TC e0 = S::ld1(a.E, ic);
+    TC hx0, hy0;
+    S::ld2(a.H, ic, hx0, hy0);
+    TC cu = 0, ve = 0;
+    const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const int qb = min(a.C4, a.V4), qm = max(a.C4, a.V4);
+    uint4 li = make_uint4(0, 0, 0, 0);
+    for (int q = 0; q < qm; ++q) {
+        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
+        const int hf = q & 1;
+        if (q < qb) {
+            TW wx[4], wy[4], wh[4];
+            ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+            ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+            ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = pos4(li, hf, u);
+                cu += (TC)wx[u] * (sH[2 * k + 1] - hy0) - (TC)wy[u] * (sH[2 * k] - hx0);
+                ve += (TC)wh[u] * (sE[k] - e0);
+            }
+        } else if (q < a.C4) {
+            TW wx[4], wy[4];
+            ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+            ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = pos4(li, hf, u);
+                cu += (TC)wx[u] * (sH[2 * k + 1] - hy0) - (TC)wy[u] * (sH[2 * k] - hx0);
+            }
+        } else {
+            TW wh[4];
+            ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ve += (TC)wh[u] * (sE[pos4(li, hf, u)] - e0);
+        }
+    }
+    if (i < a.N) {
+        const TC k = kappa_of(a, i);
+        const TC v = (a.emask[i] & 1) ? e0 + k * (cu + (TC)a.g * ve) : (TC)0;
+        S::st1(a.out, i, v);
+    }
+}
+
+template <typename TS, typename TW>
+__global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    TC* sE = lds_base<TC>();                           // 4 values per entry
+    TC* sH = sE + 4 * (int64_t)a.hmax;
+    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
+    for (int k = threadIdx.x; k < hc; k += blockDim.x) {
+        const int j = a.hpool[h0 + k];
+        S::ld3(a.E, j, sE[4 * k], sE[4 * k + 1], sE[4 * k + 2]);
+        S::ld3(a.H, j, sH[4 * k], sH[4 * k + 1], sH[4 * k + 2]);
+    }
+    __syncthreads();
+    const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
+    if (tile >= a.tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    TC ex0, ey0, ez0, hx0, hy0, hz0;
+    S::ld3(a.E, ic, ex0, ey0, ez0);
+    S::ld3(a.H, ic, hx0, hy0, hz0);
+    TC xEy = 0, xEz = 0, yEx = 0, yEz = 0, zEx = 0, zEy = 0, vx = 0, vy = 0, vz = 0;
+    const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tile * a.C4 * 3 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const int qm = max(a.C4, a.V4);
+    uint4 li = make_uint4(0, 0, 0, 0);
+    for (int q = 0; q < qm; ++q) {
+        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
+        const int hf = q & 1;
+        if (q < a.C4) {
+            TW wx[4], wy[4], wz[4];
+            ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
+            ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
+            ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = pos4(li, hf, u);
+                const TC ex = sE[4 * k] - ex0, ey = sE[4 * k + 1] - ey0, ez = sE[4 * k + 2] - ez0;
+                xEy += (TC)wx[u] * ey; xEz += (TC)wx[u] * ez;
+                yEx += (TC)wy[u] * ex; yEz += (TC)wy[u] * ez;
+                zEx += (TC)wz[u] * ex; zEy += (TC)wz[u] * ey;
+            }
+        }
+        if (q < a.V4) {
+            TW wh[4];
+            ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = pos4(li, hf, u);
+                vx += (TC)wh[u] * (sH[4 * k] - hx0);
+                vy += (TC)wh[u] * (sH[4 * k + 1] - hy0);
+                vz += (TC)wh[u] * (sH[4 * k + 2] - hz0);
+            }
+        }
+    }
+    if (i < a.N) {
+        const TC A = (TC)a.a, G = (TC)a.g;
+        S::st3(a.out, i, hx0 - A * ((yEz - zEy) - G * vx), hy0 - A * ((zEx - xEz) - G * vy),
+               hz0 - A * ((xEy - yEx) - G * vz));
+    }
+}
+
+template <typename TS, typename TW>
+__global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    TC* sE = lds_base<TC>();
+    TC* sH = sE + 4 * (int64_t)a.hmax;
+    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
+    for (int k = threadIdx.x; k < hc; k += blockDim.x) {
+        const int j = a.hpool[h0 + k];
+        S::ld3(a.E, j, sE[4 * k], sE[4 * k + 1], sE[4 * k + 2]);
+        S::ld3(a.H, j, sH[4 * k], sH[4 * k + 1], sH[4 * k + 2]);
+    }
+    __syncthreads();
+    const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
+    if (tile >= a.tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    TC ex0, ey0, ez0, hx0, hy0, hz0;
+    S::ld3(a.E, ic, ex0, ey0, ez0);
+    S::ld3(a.H, ic, hx0, hy0, hz0);
+    TC xHy = 0, xHz = 0, yHx = 0, yHz = 0, zHx = 0, zHy = 0, vx = 0, vy = 0, vz = 0;
+    const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tile * a.C4 * 3 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const int qm = max(a.C4, a.V4);
+    uint4 li = make_uint4(0, 0, 0, 0);
+    for (int q = 0; q < qm; ++q) {
+        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
+        const int hf = q & 1;
+        if (q < a.C4) {
+            TW wx[4], wy[4], wz[4];
+            ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
+            ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
+            ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = pos4(li, hf, u);
+                const TC hx = sH[4 * k] - hx0, hy = sH[4 * k + 1] - hy0, hz = sH[4 * k + 2] - hz0;
+                xHy += (TC)wx[u] * hy; xHz += (TC)wx[u] * hz;
+                yHx += (TC)wy[u] * hx; yHz += (TC)wy[u] * hz;
+                zHx += (TC)wz[u] * hx; zHy += (TC)wz[u] * hy;
+            }
+        }
+        if (q < a.V4) {
+            TW wh[4];
+            ldw4(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = pos4(li, hf, u);
+                vx += (TC)wh[u] * (sE[4 * k] - ex0);
+                vy += (TC)wh[u] * (sE[4 * k + 1] - ey0);
+                vz += (TC)wh[u] * (sE[4 * k + 2] - ez0);
+            }
+        }
+    }
+    if (i < a.N) {
+        const TC k = kappa_of(a, i), G = (TC)a.g;
+        const uint8_t m = a.emask[i];
+        const TC nx = (m & 1) ? ex0 + k * ((yHz - zHy) + G * vx) : (TC)0;
+        const TC ny = (m & 2) ? ey0 + k * ((zHx - xHz) + G * vy) : (TC)0;
+        const TC nz = (m & 4) ? ez0 + k * ((xHy - yHx) + G * vz) : (TC)0;
+        S::st3(a.out, i, nx, ny, nz);
+    }
+}
+
 // ---- per-step auxiliaries (read the device step counter) --------------------
 // src: E[node] += amp * wave[n * S + s] after the bracket (PEC nodes stay 0)
 template <typename TS>
@@ -624,6 +915,11 @@ void fill_sa(const rbffd_plan* p, const OpBlock& o, SA<TS, TW>& a, bool hupd) {
     a.eps0 = p->p.eps0;
     a.a = hupd ? p->dt / p->p.mu0 : p->dt / p->p.eps0;
     a.emask = p->E.emask;
+    a.lidx = (const uint4*)o.lidx;
+    a.hpool = o.hpool;
+    a.hoff = o.hoff;
+    a.Q8 = o.Q8;
+    a.hmax = o.hmax;
 }
 
 template <typename TS, typename TW>
@@ -636,6 +932,20 @@ void launch_half(const rbffd_plan* p, bool hupd, const void* E, const void* H, v
     a.H = (const TS*)H;
     a.out = (TS*)out;
     a.eps_r = hupd ? nullptr : eps_r;
+    if (p->collocated && o.hmax > 0 && p->var.lds) {
+        using TC = typename Store<TS>::C;
+        const dim3 grid((unsigned)o.nwg), block(RBFFD_WGT);
+        if (p->dim == 2) {
+            const size_t lds = (size_t)(((o.hmax + 3) & ~3) + 2 * o.hmax) * sizeof(TC);
+            if (hupd) hipLaunchKernelGGL((k_h2l<TS, TW>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_e2l<TS, TW>), grid, block, lds, st, a);
+        } else {
+            const size_t lds = (size_t)8 * o.hmax * sizeof(TC);
+            if (hupd) hipLaunchKernelGGL((k_h3l<TS, TW>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_e3l<TS, TW>), grid, block, lds, st, a);
+        }
+        return;
+    }
     const int wpb = p->var.block / 64;
     const dim3 grid((unsigned)cdiv(o.tiles, wpb)), block(p->var.block);
     if (p->dim == 2) {
@@ -899,12 +1209,17 @@ extern "C" int rbffd_autotune(rbffd_plan* p, rbffd_fields* f, int32_t reps, void
     // single field: workgroup size x XCD remap; K-field batch: workgroup size
     // (<= 256) x resident workgroups per CU
     const int persist_[3] = {4, 8, 16};
-    for (int x = 0; x < (p->K > 1 ? 3 : 2); ++x)
+    const bool staged = p->collocated && p->K == 1 && p->opH.hmax > 0;
+    for (int x = 0; x < (p->K > 1 ? 3 : (staged ? 4 : 2)); ++x)
         for (int b : blocks_) {
             if (p->K > 1 && b > 256) continue;
+            if (x >= 2 && b != 256) continue;     // staged kernels: one 256-thread shape
             p->var.block = b;
             if (p->K > 1) p->var.persist = persist_[x];
-            else p->var.xcd = x;
+            else {
+                p->var.xcd = x & 1;
+                p->var.lds = x >= 2 ? 1 : 0;
+            }
             rc = rbffd_step(p, f, 2, stream);   // warm
             if (rc) break;
             HIPCHK(p, hipEventRecord(e0, st));

@@ -320,4 +320,13 @@ class Solver:
         st.cur = f.cur
         v = C.c_int32()
         self.lib.rbffd_get_variant(self.plan, C.byref(v))
-        return {"block": v.value & 0xFFFF, "xcd": v.value >> 16}
+        return self.variant()
+
+    def set_variant(self, block=256, xcd=1, lds=1, persist=8):
+        check(self.lib.rbffd_set_variant(self.plan, block, xcd, lds, persist), self.plan, "set_variant")
+
+    def variant(self):
+        v = C.c_int32()
+        self.lib.rbffd_get_variant(self.plan, C.byref(v))
+        return {"block": v.value & 0xFFFF, "xcd": (v.value >> 16) & 1, "lds": (v.value >> 17) & 1,
+                "persist": (v.value >> 20) & 0xFF}
