@@ -60,6 +60,27 @@ def time_halves(s, st, reps, torch):
     return out
 
 
+def counted_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary.
+
+    Returns None unless the step-kernel source is the one the counters were
+    taken on (sha256 prefix recorded in the summary).
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_pulse2d_1M_f32.md")
+    src = os.path.join(ROOT, "paper_2508_18205_amd", "csrc", "step.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if f"sha256 prefix at measurement: {sha}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith(f"traffic_bytes_per_launch {kernel}:"):
+            return float(line.split(":")[1])
+    return None
+
+
 def cpu_baseline(w, seconds=15.0):
     """FP64 oracle on a bounded sample: the nodes in a centred sub-square."""
     import numpy as np
@@ -175,9 +196,15 @@ def main():
     log(f"H update {th * 1e6:.1f} us -> {gbs_h:.0f} GB/s ; E update {te * 1e6:.1f} us -> {gbs_e:.0f} GB/s")
     dominant = "H" if th >= te else "E"
     ach = gbs_h if dominant == "H" else gbs_e
+    staged = bool(s.variant()["lds"]) and s.sizes.N == w.N
+    kname = ("k_h2l" if dominant == "H" else "k_e2l") if staged else ("k_h2" if dominant == "H" else "k_e2")
+    traffic = None
+    if staged and args.precision == "f32" and args.scale == 1.0:
+        traffic = counted_traffic(kname)
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_h2<float,float> (H update)" if dominant == "H" else "k_e2<float,float> (E update)",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-probe scaled)",
+            "kernel": f"{kname}<float,float> ({'H' if dominant == 'H' else 'E'} update)",
             "alg_bytes_per_launch": int(bh if dominant == "H" else be),
             "avg_launch_us": round((th if dominant == "H" else te) * 1e6, 2),
             "other_half": {"achieved": round(gbs_e if dominant == "H" else gbs_h, 1),
