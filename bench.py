@@ -244,6 +244,8 @@ def main():
         wb = configs.batched_2d(scale=1.0, K=64)
         sb = Solver.from_workload(wb, precision="f32", K=64)
         stb = sb.state_batched(wb.E0_batch, np.zeros((64, wb.N, 2)))
+        vb = sb.autotune(stb, reps=5) if not args.no_tune else sb.variant()
+        stb = sb.state_batched(wb.E0_batch, np.zeros((64, wb.N, 2)))
         sb.run(stb, 20, use_graph=True)
         torch.cuda.synchronize()
         kb = 200
@@ -253,6 +255,7 @@ def main():
         torch.cuda.synchronize()
         tb = e0.elapsed_time(e1) * 1e-3
         extras["batched"] = {"value": wb.N * 64 * kb / tb, "unit": "field-node-steps/s", "K": 64, "N": wb.N,
+                             "variant": vb,
                              "steps": kb, "node_steps_per_s": wb.N * kb / tb,
                              "alg_bytes_per_field_node_step": 50.0,
                              "hbm_frac_at_50B": round(wb.N * 64 * kb / tb * 50.0 / (HBM_PEAK_GBS * 1e9), 4)}

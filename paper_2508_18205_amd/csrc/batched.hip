@@ -114,6 +114,162 @@ __global__ __launch_bounds__(256) void k_eb(BA a) {
     }
 }
 
+// ---- LDS-staged batch -----------------------------------------------------
+// Workgroup = one 64-node tile x one 16-field slice.  It copies the slice of
+// every halo node's rows (E, Hx, Hy) into LDS, then 4 threads per node each
+// update 4 fields; stencil positions (16-bit) and weights come from the same
+// tile-sliced packed arrays as the single-field kernels, one 16-byte load per
+// 4 slots shared by the node's 4 threads.
+struct BLA {
+    const float* E;
+    const float* H;
+    float* out;
+    const uint4* lidx;    // [tiles][Q8][64] x 8 u16 halo positions
+    const int32_t* hpool;
+    const int32_t* hoff;  // [tiles + 1]
+    const float* wc;      // [tiles][C4][2][64][4]
+    const float* wh;      // [tiles][V4][64][4]
+    int64_t N, tiles;
+    int K, KS, C4, V4, Q8, xcd;
+    float a, g;
+    const uint8_t* emask;
+};
+
+struct f4 {
+    float x, y, z, w;
+};
+__device__ __forceinline__ f4 ldf4(const float* p) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    return {v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ void stf4(float* p, const f4& v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void fma4(f4& acc, float w, const f4& a, const f4& b) {
+    acc.x += w * (a.x - b.x);
+    acc.y += w * (a.y - b.y);
+    acc.z += w * (a.z - b.z);
+    acc.w += w * (a.w - b.w);
+}
+__device__ __forceinline__ int posq(const uint4& v, int half, int u) {
+    const uint32_t w = half ? (u < 2 ? v.z : v.w) : (u < 2 ? v.x : v.y);
+    return (int)((u & 1) ? (w >> 16) : (w & 0xFFFFu));
+}
+
+__device__ __forceinline__ void stage_slice(const BLA& a, float* sm, int64_t tile, int ks) {
+    const int h0 = a.hoff[tile], hc = a.hoff[tile + 1] - h0;
+    const int64_t K = a.K;
+    const int kof = ks * RBFFD_KSLICE;
+    for (int it = threadIdx.x; it < hc * 12; it += blockDim.x) {
+        const int k = it / 12, r = it - k * 12, c = r >> 2, q = r & 3;
+        const int64_t j = a.hpool[h0 + k];
+        const float* src = c == 0 ? a.E + j * K : a.H + (j * 2 + (c - 1)) * K;
+        stf4(sm + (k * 3 + c) * RBFFD_KSLICE + q * 4, ldf4(src + kof + q * 4));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_hbl(BLA a) {
+    extern __shared__ __align__(16) float sm[];
+    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int64_t tile = wg / a.KS;
+    const int ks = wg % a.KS;
+    stage_slice(a, sm, tile, ks);
+    __syncthreads();
+    const int nl = threadIdx.x >> 2, fq = threadIdx.x & 3;
+    const int64_t i = tile * RBFFD_TILE + nl;
+    if (i >= a.N) return;
+    const int64_t K = a.K;
+    const int k0 = ks * RBFFD_KSLICE + fq * 4;
+    const f4 e0 = ldf4(a.E + i * K + k0), hx0 = ldf4(a.H + (i * 2) * K + k0), hy0 = ldf4(a.H + (i * 2 + 1) * K + k0);
+    f4 dx{0, 0, 0, 0}, dy{0, 0, 0, 0}, vx{0, 0, 0, 0}, vy{0, 0, 0, 0};
+    const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + nl;
+    const float* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + nl) * 4;
+    const float* ph = a.wh + (tile * a.V4 * RBFFD_TILE + nl) * 4;
+    const int qm = max(a.C4, a.V4);
+    uint4 li = make_uint4(0, 0, 0, 0);
+    for (int q = 0; q < qm; ++q) {
+        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
+        const int hf = q & 1;
+        if (q < a.C4) {
+            const f4 wx = ldf4(pc + (q * 2 + 0) * RBFFD_TILE * 4), wy = ldf4(pc + (q * 2 + 1) * RBFFD_TILE * 4);
+            const float wxs[4] = {wx.x, wx.y, wx.z, wx.w}, wys[4] = {wy.x, wy.y, wy.z, wy.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const f4 e = ldf4(sm + (posq(li, hf, u) * 3 + 0) * RBFFD_KSLICE + fq * 4);
+                fma4(dx, wxs[u], e, e0);
+                fma4(dy, wys[u], e, e0);
+            }
+        }
+        if (q < a.V4) {
+            const f4 wh = ldf4(ph + q * RBFFD_TILE * 4);
+            const float whs[4] = {wh.x, wh.y, wh.z, wh.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = posq(li, hf, u);
+                fma4(vx, whs[u], ldf4(sm + (k * 3 + 1) * RBFFD_KSLICE + fq * 4), hx0);
+                fma4(vy, whs[u], ldf4(sm + (k * 3 + 2) * RBFFD_KSLICE + fq * 4), hy0);
+            }
+        }
+    }
+    const float A = a.a, G = a.g;
+    stf4(a.out + (i * 2) * K + k0, {hx0.x + A * (-dy.x + G * vx.x), hx0.y + A * (-dy.y + G * vx.y),
+                                    hx0.z + A * (-dy.z + G * vx.z), hx0.w + A * (-dy.w + G * vx.w)});
+    stf4(a.out + (i * 2 + 1) * K + k0, {hy0.x + A * (dx.x + G * vy.x), hy0.y + A * (dx.y + G * vy.y),
+                                        hy0.z + A * (dx.z + G * vy.z), hy0.w + A * (dx.w + G * vy.w)});
+}
+
+__global__ __launch_bounds__(256) void k_ebl(BLA a) {
+    extern __shared__ __align__(16) float sm[];
+    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int64_t tile = wg / a.KS;
+    const int ks = wg % a.KS;
+    stage_slice(a, sm, tile, ks);
+    __syncthreads();
+    const int nl = threadIdx.x >> 2, fq = threadIdx.x & 3;
+    const int64_t i = tile * RBFFD_TILE + nl;
+    if (i >= a.N) return;
+    const int64_t K = a.K;
+    const int k0 = ks * RBFFD_KSLICE + fq * 4;
+    const f4 e0 = ldf4(a.E + i * K + k0), hx0 = ldf4(a.H + (i * 2) * K + k0), hy0 = ldf4(a.H + (i * 2 + 1) * K + k0);
+    f4 cu{0, 0, 0, 0}, ve{0, 0, 0, 0};
+    const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + nl;
+    const float* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + nl) * 4;
+    const float* ph = a.wh + (tile * a.V4 * RBFFD_TILE + nl) * 4;
+    const int qm = max(a.C4, a.V4);
+    uint4 li = make_uint4(0, 0, 0, 0);
+    for (int q = 0; q < qm; ++q) {
+        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
+        const int hf = q & 1;
+        if (q < a.C4) {
+            const f4 wx = ldf4(pc + (q * 2 + 0) * RBFFD_TILE * 4), wy = ldf4(pc + (q * 2 + 1) * RBFFD_TILE * 4);
+            const float wxs[4] = {wx.x, wx.y, wx.z, wx.w}, wys[4] = {wy.x, wy.y, wy.z, wy.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = posq(li, hf, u);
+                // curl H = D^dx Hy - D^dy Hx, in the single-field kernels' order
+                const f4 hx = ldf4(sm + (k * 3 + 1) * RBFFD_KSLICE + fq * 4);
+                const f4 hy = ldf4(sm + (k * 3 + 2) * RBFFD_KSLICE + fq * 4);
+                cu.x += wxs[u] * (hy.x - hy0.x) - wys[u] * (hx.x - hx0.x);
+                cu.y += wxs[u] * (hy.y - hy0.y) - wys[u] * (hx.y - hx0.y);
+                cu.z += wxs[u] * (hy.z - hy0.z) - wys[u] * (hx.z - hx0.z);
+                cu.w += wxs[u] * (hy.w - hy0.w) - wys[u] * (hx.w - hx0.w);
+            }
+        }
+        if (q < a.V4) {
+            const f4 wh = ldf4(ph + q * RBFFD_TILE * 4);
+            const float whs[4] = {wh.x, wh.y, wh.z, wh.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                fma4(ve, whs[u], ldf4(sm + (posq(li, hf, u) * 3 + 0) * RBFFD_KSLICE + fq * 4), e0);
+        }
+    }
+    const float A = a.a, G = a.g;
+    const bool keep = a.emask[i] & 1;
+    stf4(a.out + i * K + k0, keep ? f4{e0.x + A * (cu.x + G * ve.x), e0.y + A * (cu.y + G * ve.y),
+                                       e0.z + A * (cu.z + G * ve.z), e0.w + A * (cu.w + G * ve.w)}
+                                  : f4{0, 0, 0, 0});
+}
+
 BA make_args(const rbffd_plan* p) {
     const OpBlock& o = p->opH;
     BA a{};
@@ -131,7 +287,44 @@ BA make_args(const rbffd_plan* p) {
     return a;
 }
 
+bool staged(const rbffd_plan* p) {
+    return p->var.lds && p->opH.hmax > 0 && (p->K % RBFFD_KSLICE) == 0;
+}
+
+void launch_pair_staged(const rbffd_plan* p, const rbffd_fields* f, int c, hipStream_t st) {
+    const int o = 1 - c;
+    const OpBlock& ob = p->opH;
+    BLA a{};
+    a.lidx = (const uint4*)ob.lidx;
+    a.hpool = ob.hpool;
+    a.hoff = ob.hoff;
+    a.wc = (const float*)ob.pwc;
+    a.wh = (const float*)ob.pwh;
+    a.N = ob.Nt;
+    a.tiles = ob.tiles;
+    a.K = p->K;
+    a.KS = p->K / RBFFD_KSLICE;
+    a.C4 = ob.C4;
+    a.V4 = ob.V4;
+    a.Q8 = ob.Q8;
+    a.xcd = p->var.xcd;
+    a.g = (float)p->gamma;
+    a.emask = p->E.emask;
+    const dim3 grid((unsigned)(ob.tiles * a.KS)), block(256);
+    const size_t lds = (size_t)ob.hmax * 3 * RBFFD_KSLICE * sizeof(float);
+    a.E = (const float*)f->E[c];
+    a.H = (const float*)f->H[c];
+    a.out = (float*)f->H[o];
+    a.a = (float)(p->dt / p->p.mu0);
+    hipLaunchKernelGGL(k_hbl, grid, block, lds, st, a);
+    a.H = (const float*)f->H[o];
+    a.out = (float*)f->E[o];
+    a.a = (float)(p->dt / p->p.eps0);
+    hipLaunchKernelGGL(k_ebl, grid, block, lds, st, a);
+}
+
 void launch_pair(const rbffd_plan* p, const rbffd_fields* f, int c, hipStream_t st) {
+    if (staged(p)) return launch_pair_staged(p, f, c, st);
     const int o = 1 - c;
     BA a = make_args(p);
     int dev = 0, cus = 256;

@@ -90,13 +90,13 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int K, bool adjoint) {
     if (!o.cross) {
         o.st_union = b.take<int32_t>(o.Nt * o.ns);
         o.pidx = b.take_bytes(T * o.S4 * 16);
-        if (K == 1) {
-            o.Q8 = (int)cdiv(o.ns - 1, 8);
-            o.nwg = cdiv(o.tiles, RBFFD_WGT / RBFFD_TILE);
-            o.lidx = b.take<uint16_t>(T * o.Q8 * 8);
-            o.hpool = b.take<int32_t>(o.Nt * o.ns);
-            o.hoff = b.take<int32_t>(o.nwg + 1);
-        }
+        // halo lists: 256-node workgroup tiles for the single-field kernels,
+        // 64-node tiles (node-major positions) for the K-field batch
+        o.Q8 = (int)cdiv(o.ns - 1, 8);
+        o.nwg = K == 1 ? cdiv(o.tiles, RBFFD_WGT / RBFFD_TILE) : o.tiles;
+        o.lidx = b.take<uint16_t>(T * o.Q8 * 8);
+        o.hpool = b.take<int32_t>(o.Nt * o.ns);
+        o.hoff = b.take<int32_t>(o.nwg + 1);
     } else {
         o.st_curl = b.take<int32_t>(o.Nt * o.n);
         o.st_hv = o.nh > 0 ? b.take<int32_t>(o.Nt * o.nh) : nullptr;

@@ -637,11 +637,11 @@ __global__ void k_tweights(const int32_t* tsrc, const int32_t* tslot, int64_t E,
 // the slot's node in that list.  Built from one global sort of
 // (tile, source) keys.
 // ---------------------------------------------------------------------------
-__global__ void k_hkeys(const int32_t* st, int64_t N, int ns, uint64_t* keys) {
+__global__ void k_hkeys(const int32_t* st, int64_t N, int ns, int tsz, uint64_t* keys) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= N * ns) return;
     const int64_t i = e / ns;
-    keys[e] = ((uint64_t)(i / RBFFD_WGT) << 32) | (uint64_t)(uint32_t)st[e];
+    keys[e] = ((uint64_t)(i / tsz) << 32) | (uint64_t)(uint32_t)st[e];
 }
 
 __global__ void k_hflags(const uint64_t* sk, int64_t E, int32_t* flag) {
@@ -672,13 +672,13 @@ __device__ __forceinline__ int lower_pos(const int32_t* a, int n, int32_t v) {
 }
 
 __global__ void k_hlocal(const int32_t* st, int64_t N, int ns, const int32_t* pool, const int32_t* hoff, int Q8,
-                         int64_t tiles, uint16_t* lidx) {
+                         int64_t tiles, int tsz, uint16_t* lidx) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= tiles * RBFFD_TILE) return;
     const int64_t tile = g / RBFFD_TILE;
     const int lane = (int)(g % RBFFD_TILE);
     const bool real = g < N;
-    const int64_t wg = g / RBFFD_WGT;
+    const int64_t wg = g / tsz;
     const int32_t* L = pool + hoff[wg];
     const int cnt = hoff[wg + 1] - hoff[wg];
     const int self = real ? lower_pos(L, cnt, (int32_t)g) : 0;
@@ -895,7 +895,7 @@ int64_t setup_ws_bytes(const rbffd_plan* p) {
     }
     w.take<int32_t>(64);   // status
     int64_t need = w.off;
-    if (p->collocated && p->K == 1) {
+    if (p->collocated) {
         WS t{nullptr};
         const int64_t E = p->E.N * p->ns;
         t.take<uint64_t>(E);
@@ -1187,15 +1187,17 @@ int build_halos(rbffd_plan* p, void* wsp, hipStream_t st) {
     size_t tb = key_sort_temp_bytes(E), sb = scan_temp_bytes(E);
     void* temp = w.take<char>((int64_t)tb);
     void* stemp = w.take<char>((int64_t)sb);
-    hipLaunchKernelGGL(k_hkeys, dim3(blocks(E)), dim3(256), 0, st, o.st_union, N, (int)ns, kin);
+    const bool batch = p->K > 1;
+    const int tsz = batch ? RBFFD_TILE : RBFFD_WGT;
+    hipLaunchKernelGGL(k_hkeys, dim3(blocks(E)), dim3(256), 0, st, o.st_union, N, (int)ns, tsz, kin);
     int end_bit = 32;
     while (end_bit < 64 && ((uint64_t)1 << (end_bit - 32)) <= (uint64_t)o.nwg) ++end_bit;
     HIPCHK(p, hipcub::DeviceRadixSort::SortKeys(temp, tb, kin, kout, (int)E, 0, end_bit, st));
     hipLaunchKernelGGL(k_hflags, dim3(blocks(E)), dim3(256), 0, st, kout, E, flag);
     HIPCHK(p, hipcub::DeviceScan::ExclusiveSum(stemp, sb, flag, pos, (int)E, st));
     hipLaunchKernelGGL(k_hcompact, dim3(blocks(E)), dim3(256), 0, st, kout, flag, pos, E, o.hpool, o.hoff, o.nwg);
-    hipLaunchKernelGGL(k_hlocal, dim3(blocks(o.tiles * RBFFD_TILE)), dim3(256), 0, st, o.st_union, N, (int)ns, o.hpool,
-                       o.hoff, o.Q8, o.tiles, o.lidx);
+    hipLaunchKernelGGL(k_hlocal, dim3(blocks(o.tiles * RBFFD_TILE)), dim3(256), 0, st, o.st_union, N, (int)ns,
+                       o.hpool, o.hoff, o.Q8, o.tiles, tsz, o.lidx);
     HIPCHK(p, hipGetLastError());
     std::vector<int32_t> off(o.nwg + 1);
     HIPCHK(p, hipMemcpyAsync(off.data(), o.hoff, (o.nwg + 1) * 4, hipMemcpyDeviceToHost, st));
@@ -1204,8 +1206,10 @@ int build_halos(rbffd_plan* p, void* wsp, hipStream_t st) {
     for (int64_t t = 0; t < o.nwg; ++t) mx = std::max(mx, off[t + 1] - off[t]);
     // staging only when a workgroup's list fits the LDS budget and 16-bit positions
     const int fb = field_elem_bytes(p->p.fdtype) == 8 ? 8 : 4;
-    const int64_t per = (int64_t)(p->FE + p->FH) * fb;
-    o.hmax = (mx < 65536 && (int64_t)mx * per <= RBFFD_LDS_BUDGET) ? mx : 0;
+    // single field: one value per component; batch: a 16-field slice per component
+    const int64_t per = batch ? (int64_t)(p->fe_comp + p->fh_comp) * RBFFD_KSLICE * 4 : (int64_t)(p->FE + p->FH) * fb;
+    const int64_t budget = batch ? RBFFD_LDS_BUDGET_BATCH : RBFFD_LDS_BUDGET;
+    o.hmax = (mx < 65536 && (int64_t)mx * per <= budget) ? mx : 0;
     p->opE = p->opH;
     return RBFFD_OK;
 }
@@ -1239,7 +1243,7 @@ extern "C" int rbffd_weights(rbffd_plan* p, void* arena, void* ws, void* stream)
     if (rc) return rc;
     if ((rc = setup_weights(p, ws, st))) return rc;
     if ((rc = pack_all(p, ws, st))) return rc;
-    if (p->collocated && p->K == 1 && (rc = build_halos(p, ws, st))) return rc;
+    if (p->collocated && (rc = build_halos(p, ws, st))) return rc;
     if (p->p.adjoint && (rc = build_transpose(p, ws, st))) return rc;
     HIPCHK(p, hipStreamSynchronize(st));
     p->ready = true;

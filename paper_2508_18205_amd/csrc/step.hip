@@ -1200,40 +1200,43 @@ extern "C" int rbffd_autotune(rbffd_plan* p, rbffd_fields* f, int32_t reps, void
     if (rc) return rc;
     if (reps < 1) reps = 1;
     hipStream_t st = (hipStream_t)stream;
-    const int blocks_[4] = {64, 128, 256, 512};
+    // candidate launch variants: single field -- workgroup size x XCD remap
+    // for the global-gather kernels, plus the LDS-staged kernels (fixed
+    // shape) with and without the remap; K-field batch -- workgroup size x
+    // resident workgroups per CU for the global kernels, plus the staged one
+    std::vector<Variant> cand;
+    const bool staged = p->collocated && p->opH.hmax > 0;
+    for (int b : {64, 128, 256, 512}) {
+        if (p->K > 1) {
+            if (b > 256) continue;
+            for (int pe : {4, 8, 16}) cand.push_back(Variant{b, 1, pe, 0});
+        } else {
+            for (int x : {0, 1}) cand.push_back(Variant{b, x, 8, 0});
+        }
+    }
+    if (staged)
+        for (int x : {0, 1}) cand.push_back(Variant{256, x, 8, 1});
     Variant best = p->var;
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
     HIPCHK(p, hipEventCreate(&e0));
     HIPCHK(p, hipEventCreate(&e1));
-    // single field: workgroup size x XCD remap; K-field batch: workgroup size
-    // (<= 256) x resident workgroups per CU
-    const int persist_[3] = {4, 8, 16};
-    const bool staged = p->collocated && p->K == 1 && p->opH.hmax > 0;
-    for (int x = 0; x < (p->K > 1 ? 3 : (staged ? 4 : 2)); ++x)
-        for (int b : blocks_) {
-            if (p->K > 1 && b > 256) continue;
-            if (x >= 2 && b != 256) continue;     // staged kernels: one 256-thread shape
-            p->var.block = b;
-            if (p->K > 1) p->var.persist = persist_[x];
-            else {
-                p->var.xcd = x & 1;
-                p->var.lds = x >= 2 ? 1 : 0;
-            }
-            rc = rbffd_step(p, f, 2, stream);   // warm
-            if (rc) break;
-            HIPCHK(p, hipEventRecord(e0, st));
-            rc = rbffd_step(p, f, reps, stream);
-            if (rc) break;
-            HIPCHK(p, hipEventRecord(e1, st));
-            HIPCHK(p, hipEventSynchronize(e1));
-            float ms = 0;
-            HIPCHK(p, hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = p->var;
-            }
+    for (const Variant& v : cand) {
+        p->var = v;
+        rc = rbffd_step(p, f, 2, stream);   // warm
+        if (rc) break;
+        HIPCHK(p, hipEventRecord(e0, st));
+        rc = rbffd_step(p, f, reps, stream);
+        if (rc) break;
+        HIPCHK(p, hipEventRecord(e1, st));
+        HIPCHK(p, hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(p, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
         }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->var = best;

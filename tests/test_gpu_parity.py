@@ -230,10 +230,12 @@ def test_run_energy_sources_receivers_graph():
     assert np.abs(T - tr).max() <= 1e-12 * np.abs(tr).max()
 
 
-def test_batched_equals_single_runs():
-    _announce("K-field batch vs single runs")
+@pytest.mark.parametrize("lds", [1, 0])
+def test_batched_equals_single_runs(lds):
+    _announce(f"K-field batch vs single runs (staged={lds})")
     w = configs.batched_2d(n_side=60, K=64, steps=100, chat=1e-3)
     sb = Solver.from_workload(w, precision="f32", K=64)
+    sb.set_variant(block=256, xcd=1, lds=lds, persist=8)
     stb = sb.state_batched(w.E0_batch, np.zeros((64, w.N, 2)))
     sb.run(stb, w.steps, use_graph=True)
     Eb = sb.to_original(stb.E)             # [N, 1, K]
