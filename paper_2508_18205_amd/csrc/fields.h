@@ -88,21 +88,49 @@ template <> struct Store<bf16s> {
     }
 };
 
+// Packed weights and stencil positions are streamed once per half step:
+// load them non-temporally so that they do not displace the gathered field
+// values in L2.
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+
 // four consecutive packed weights
 __device__ __forceinline__ void ldw4(const float* p, float (&w)[4]) {
-    const float4 v = *reinterpret_cast<const float4*>(p);
+    const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
     w[0] = v.x;
     w[1] = v.y;
     w[2] = v.z;
     w[3] = v.w;
 }
 __device__ __forceinline__ void ldw4(const double* p, double (&w)[4]) {
+    const nt_d2 a = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+    const nt_d2 b = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p) + 1);
+    w[0] = a.x;
+    w[1] = a.y;
+    w[2] = b.x;
+    w[3] = b.y;
+}
+// plain (cached) loads for the global-gather kernels, whose weight stream
+// competes less with the L2-resident gathers than with the staged halo copies
+__device__ __forceinline__ void ldw4p(const float* p, float (&w)[4]) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    w[0] = v.x;
+    w[1] = v.y;
+    w[2] = v.z;
+    w[3] = v.w;
+}
+__device__ __forceinline__ void ldw4p(const double* p, double (&w)[4]) {
     const double2 a = reinterpret_cast<const double2*>(p)[0];
     const double2 b = reinterpret_cast<const double2*>(p)[1];
     w[0] = a.x;
     w[1] = a.y;
     w[2] = b.x;
     w[3] = b.y;
+}
+__device__ __forceinline__ uint4 ldu4s(const uint4* p) {
+    const nt_u4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ int idx4(const int4& j, int u) {
     return u == 0 ? j.x : (u == 1 ? j.y : (u == 2 ? j.z : j.w));

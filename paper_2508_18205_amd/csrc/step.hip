@@ -87,9 +87,9 @@ __global__ __launch_bounds__(512) void k_h2(SA<TS, TW> a) {
     for (; q < qb; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4], wh[4];
-        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
-        ldw4(ph + q * RBFFD_TILE * 4, wh);
+        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int jj = idx4(j, u);
@@ -105,8 +105,8 @@ __global__ __launch_bounds__(512) void k_h2(SA<TS, TW> a) {
     for (; q < a.C4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4];
-        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const TC de = S::ld1(a.E, idx4(j, u)) - e0;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(512) void k_h2(SA<TS, TW> a) {
     for (; q < a.V4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wh[4];
-        ldw4(ph + q * RBFFD_TILE * 4, wh);
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             TC hx, hy;
@@ -153,9 +153,9 @@ __global__ __launch_bounds__(512) void k_e2(SA<TS, TW> a) {
     for (; q < qb; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4], wh[4];
-        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
-        ldw4(ph + q * RBFFD_TILE * 4, wh);
+        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int jj = idx4(j, u);
@@ -168,8 +168,8 @@ __global__ __launch_bounds__(512) void k_e2(SA<TS, TW> a) {
     for (; q < a.C4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4];
-        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             TC hx, hy;
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(512) void k_e2(SA<TS, TW> a) {
     for (; q < a.V4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wh[4];
-        ldw4(ph + q * RBFFD_TILE * 4, wh);
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) ve += (TC)wh[u] * (S::ld1(a.E, idx4(j, u)) - e0);
     }
@@ -214,8 +214,8 @@ __global__ __launch_bounds__(512) void k_h2x(SA<TS, TW> a) {
     for (int q = 0; q < a.C4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4];
-        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const TC de = S::ld1(a.E, idx4(j, u)) - e0;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(512) void k_h2x(SA<TS, TW> a) {
     for (int q = 0; q < a.V4; ++q) {
         const int4 j = pj[q * RBFFD_TILE];
         TW wh[4];
-        ldw4(ph + q * RBFFD_TILE * 4, wh);
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             TC hx, hy;
@@ -261,8 +261,8 @@ __global__ __launch_bounds__(512) void k_e2x(SA<TS, TW> a) {
     for (int q = 0; q < a.C4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4];
-        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             TC hx, hy;
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(512) void k_e2x(SA<TS, TW> a) {
     for (int q = 0; q < a.V4; ++q) {
         const int4 j = pj[q * RBFFD_TILE];
         TW wh[4];
-        ldw4(ph + q * RBFFD_TILE * 4, wh);
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) ve += (TC)wh[u] * (S::ld1(a.E, idx4(j, u)) - e0);
     }
@@ -307,10 +307,10 @@ __global__ __launch_bounds__(512) void k_h3(SA<TS, TW> a) {
     for (; q < qb; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4], wz[4], wh[4];
-        ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
-        ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
-        ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
-        ldw4(ph + q * RBFFD_TILE * 4, wh);
+        ldw4p(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
+        ldw4p(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int jj = idx4(j, u);
@@ -329,9 +329,9 @@ __global__ __launch_bounds__(512) void k_h3(SA<TS, TW> a) {
     for (; q < a.C4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4], wz[4];
-        ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
-        ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
-        ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
+        ldw4p(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
+        ldw4p(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             TC ex, ey, ez;
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(512) void k_h3(SA<TS, TW> a) {
     for (; q < a.V4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wh[4];
-        ldw4(ph + q * RBFFD_TILE * 4, wh);
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             TC hx, hy, hz;
@@ -384,10 +384,10 @@ __global__ __launch_bounds__(512) void k_e3(SA<TS, TW> a) {
     for (; q < qb; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4], wz[4], wh[4];
-        ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
-        ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
-        ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
-        ldw4(ph + q * RBFFD_TILE * 4, wh);
+        ldw4p(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
+        ldw4p(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int jj = idx4(j, u);
@@ -406,9 +406,9 @@ __global__ __launch_bounds__(512) void k_e3(SA<TS, TW> a) {
     for (; q < a.C4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4], wz[4];
-        ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
-        ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
-        ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
+        ldw4p(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
+        ldw4p(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             TC hx, hy, hz;
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(512) void k_e3(SA<TS, TW> a) {
     for (; q < a.V4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wh[4];
-        ldw4(ph + q * RBFFD_TILE * 4, wh);
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             TC ex, ey, ez;
@@ -454,6 +454,43 @@ __device__ __forceinline__ int pos4(const uint4& v, int half, int u) {
     return (int)((u & 1) ? (w >> 16) : (w & 0xFFFFu));
 }
 
+// one 16-byte (FP32) or two 16-byte (FP64) LDS accesses per 3-vector entry
+__device__ __forceinline__ void st_lds4(float* p, const float (&v)[3]) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], 0.0f);
+}
+__device__ __forceinline__ void st_lds4(double* p, const double (&v)[3]) {
+    reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2*>(p)[1] = make_double2(v[2], 0.0);
+}
+__device__ __forceinline__ void ld_lds4(const float* p, float (&v)[3]) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+}
+__device__ __forceinline__ void ld_lds4(const double* p, double (&v)[3]) {
+    const double2 a = reinterpret_cast<const double2*>(p)[0];
+    const double2 b = reinterpret_cast<const double2*>(p)[1];
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+}
+
+__device__ __forceinline__ void ld_lds2(const float* p, float& x, float& y) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    x = t.x;
+    y = t.y;
+}
+__device__ __forceinline__ void ld_lds2(const double* p, double& x, double& y) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    x = t.x;
+    y = t.y;
+}
+__device__ __forceinline__ void st_lds2(float* p, float x, float y) { *reinterpret_cast<float2*>(p) = make_float2(x, y); }
+__device__ __forceinline__ void st_lds2(double* p, double x, double y) {
+    *reinterpret_cast<double2*>(p) = make_double2(x, y);
+}
+
 template <typename TC>
 __device__ __forceinline__ TC* lds_base() {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -471,7 +508,9 @@ __global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
     for (int k = threadIdx.x; k < hc; k += blockDim.x) {
         const int j = a.hpool[h0 + k];
         sE[k] = S::ld1(a.E, j);
-        S::ld2(a.H, j, sH[2 * k], sH[2 * k + 1]);
+        TC hx, hy;
+        S::ld2(a.H, j, hx, hy);
+        st_lds2(sH + 2 * k, hx, hy);
     }
     __syncthreads();
     const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
@@ -489,7 +528,7 @@ __global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
     const int qb = min(a.C4, a.V4), qm = max(a.C4, a.V4);
     uint4 li = make_uint4(0, 0, 0, 0);
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
+        if ((q & 1) == 0) li = ldu4s(pl + (q >> 1) * RBFFD_TILE);
         const int hf = q & 1;
         if (q < qb) {
             TW wx[4], wy[4], wh[4];
@@ -502,8 +541,10 @@ __global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
                 const TC de = sE[k] - e0;
                 dx += (TC)wx[u] * de;
                 dy += (TC)wy[u] * de;
-                vx += (TC)wh[u] * (sH[2 * k] - hx0);
-                vy += (TC)wh[u] * (sH[2 * k + 1] - hy0);
+                TC hx, hy;
+                ld_lds2(sH + 2 * k, hx, hy);
+                vx += (TC)wh[u] * (hx - hx0);
+                vy += (TC)wh[u] * (hy - hy0);
             }
         } else if (q < a.C4) {
             TW wx[4], wy[4];
@@ -521,8 +562,10 @@ __global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = pos4(li, hf, u);
-                vx += (TC)wh[u] * (sH[2 * k] - hx0);
-                vy += (TC)wh[u] * (sH[2 * k + 1] - hy0);
+                TC hx, hy;
+                ld_lds2(sH + 2 * k, hx, hy);
+                vx += (TC)wh[u] * (hx - hx0);
+                vy += (TC)wh[u] * (hy - hy0);
             }
         }
     }
@@ -543,7 +586,9 @@ __global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
     for (int k = threadIdx.x; k < hc; k += blockDim.x) {
         const int j = a.hpool[h0 + k];
         sE[k] = S::ld1(a.E, j);
-        S::ld2(a.H, j, sH[2 * k], sH[2 * k + 1]);
+        TC hx, hy;
+        S::ld2(a.H, j, hx, hy);
+        st_lds2(sH + 2 * k, hx, hy);
     }
     __syncthreads();
     const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
@@ -561,7 +606,7 @@ __global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
     const int qb = min(a.C4, a.V4), qm = max(a.C4, a.V4);
     uint4 li = make_uint4(0, 0, 0, 0);
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
+        if ((q & 1) == 0) li = ldu4s(pl + (q >> 1) * RBFFD_TILE);
         const int hf = q & 1;
         if (q < qb) {
             TW wx[4], wy[4], wh[4];
@@ -571,7 +616,9 @@ __global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = pos4(li, hf, u);
-                cu += (TC)wx[u] * (sH[2 * k + 1] - hy0) - (TC)wy[u] * (sH[2 * k] - hx0);
+                TC hx, hy;
+                ld_lds2(sH + 2 * k, hx, hy);
+                cu += (TC)wx[u] * (hy - hy0) - (TC)wy[u] * (hx - hx0);
                 ve += (TC)wh[u] * (sE[k] - e0);
             }
         } else if (q < a.C4) {
@@ -581,7 +628,9 @@ __global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = pos4(li, hf, u);
-                cu += (TC)wx[u] * (sH[2 * k + 1] - hy0) - (TC)wy[u] * (sH[2 * k] - hx0);
+                TC hx, hy;
+                ld_lds2(sH + 2 * k, hx, hy);
+                cu += (TC)wx[u] * (hy - hy0) - (TC)wy[u] * (hx - hx0);
             }
         } else {
             TW wh[4];
@@ -607,8 +656,11 @@ __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
     for (int k = threadIdx.x; k < hc; k += blockDim.x) {
         const int j = a.hpool[h0 + k];
-        S::ld3(a.E, j, sE[4 * k], sE[4 * k + 1], sE[4 * k + 2]);
-        S::ld3(a.H, j, sH[4 * k], sH[4 * k + 1], sH[4 * k + 2]);
+        TC e[3], hh[3];
+        S::ld3(a.E, j, e[0], e[1], e[2]);
+        S::ld3(a.H, j, hh[0], hh[1], hh[2]);
+        st_lds4(sE + 4 * k, e);
+        st_lds4(sH + 4 * k, hh);
     }
     __syncthreads();
     const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
@@ -626,7 +678,7 @@ __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
     const int qm = max(a.C4, a.V4);
     uint4 li = make_uint4(0, 0, 0, 0);
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
+        if ((q & 1) == 0) li = ldu4s(pl + (q >> 1) * RBFFD_TILE);
         const int hf = q & 1;
         if (q < a.C4) {
             TW wx[4], wy[4], wz[4];
@@ -636,7 +688,9 @@ __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = pos4(li, hf, u);
-                const TC ex = sE[4 * k] - ex0, ey = sE[4 * k + 1] - ey0, ez = sE[4 * k + 2] - ez0;
+                TC v[3];
+                ld_lds4(sE + 4 * k, v);
+                const TC ex = v[0] - ex0, ey = v[1] - ey0, ez = v[2] - ez0;
                 xEy += (TC)wx[u] * ey; xEz += (TC)wx[u] * ez;
                 yEx += (TC)wy[u] * ex; yEz += (TC)wy[u] * ez;
                 zEx += (TC)wz[u] * ex; zEy += (TC)wz[u] * ey;
@@ -647,10 +701,11 @@ __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
             ldw4(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int k = pos4(li, hf, u);
-                vx += (TC)wh[u] * (sH[4 * k] - hx0);
-                vy += (TC)wh[u] * (sH[4 * k + 1] - hy0);
-                vz += (TC)wh[u] * (sH[4 * k + 2] - hz0);
+                TC v[3];
+                ld_lds4(sH + 4 * pos4(li, hf, u), v);
+                vx += (TC)wh[u] * (v[0] - hx0);
+                vy += (TC)wh[u] * (v[1] - hy0);
+                vz += (TC)wh[u] * (v[2] - hz0);
             }
         }
     }
@@ -671,8 +726,11 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
     for (int k = threadIdx.x; k < hc; k += blockDim.x) {
         const int j = a.hpool[h0 + k];
-        S::ld3(a.E, j, sE[4 * k], sE[4 * k + 1], sE[4 * k + 2]);
-        S::ld3(a.H, j, sH[4 * k], sH[4 * k + 1], sH[4 * k + 2]);
+        TC e[3], hh[3];
+        S::ld3(a.E, j, e[0], e[1], e[2]);
+        S::ld3(a.H, j, hh[0], hh[1], hh[2]);
+        st_lds4(sE + 4 * k, e);
+        st_lds4(sH + 4 * k, hh);
     }
     __syncthreads();
     const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
@@ -690,7 +748,7 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
     const int qm = max(a.C4, a.V4);
     uint4 li = make_uint4(0, 0, 0, 0);
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
+        if ((q & 1) == 0) li = ldu4s(pl + (q >> 1) * RBFFD_TILE);
         const int hf = q & 1;
         if (q < a.C4) {
             TW wx[4], wy[4], wz[4];
@@ -700,7 +758,9 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = pos4(li, hf, u);
-                const TC hx = sH[4 * k] - hx0, hy = sH[4 * k + 1] - hy0, hz = sH[4 * k + 2] - hz0;
+                TC v[3];
+                ld_lds4(sH + 4 * k, v);
+                const TC hx = v[0] - hx0, hy = v[1] - hy0, hz = v[2] - hz0;
                 xHy += (TC)wx[u] * hy; xHz += (TC)wx[u] * hz;
                 yHx += (TC)wy[u] * hx; yHz += (TC)wy[u] * hz;
                 zHx += (TC)wz[u] * hx; zHy += (TC)wz[u] * hy;
@@ -711,10 +771,11 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
             ldw4(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int k = pos4(li, hf, u);
-                vx += (TC)wh[u] * (sE[4 * k] - ex0);
-                vy += (TC)wh[u] * (sE[4 * k + 1] - ey0);
-                vz += (TC)wh[u] * (sE[4 * k + 2] - ez0);
+                TC v[3];
+                ld_lds4(sE + 4 * pos4(li, hf, u), v);
+                vx += (TC)wh[u] * (v[0] - ex0);
+                vy += (TC)wh[u] * (v[1] - ey0);
+                vz += (TC)wh[u] * (v[2] - ez0);
             }
         }
     }

@@ -269,3 +269,41 @@ def test_staged_and_global_kernels_agree(case):
         out.append((s.E_original(st), s.H_original(st)))
     assert s.sizes.N == w.N
     assert (out[0][0] == out[1][0]).all() and (out[0][1] == out[1][1]).all()
+
+
+def test_rcm_order_bit_exact():
+    _announce("RCM order")
+    xyz, flags, h = nodes.jittered_grid((23, 19), seed=29)
+    w = configs.Workload("rcm", 2, xyz, flags, h, 12, 2, 2, 31, 1e-3, 50)
+    w.E0, w.H0 = fields.gaussian_pulse(xyz, (0.5, 0.5), 0.1)
+    s = Solver.from_workload(w, precision="f64", reorder="RCM")
+    ref = reorder.rcm_order(knn.knn(xyz, w.n))
+    assert (s.perm == ref).all()
+    # the step is independent of the node order
+    s2 = Solver.from_workload(w, precision="f64")
+    outs = []
+    for sv in (s, s2):
+        st = sv.state(w.E0, w.H0)
+        sv.step(st, w.steps)
+        outs.append(sv.E_original(st))
+    assert ostep.rel_l2(outs[0], outs[1]) < 1e-13
+
+
+@pytest.mark.parametrize("mode", ["FD", "VFD"])
+def test_periodic_pulse_paper_setup_on_gpu(mode):
+    # eq. 21 on the periodic [0, 200] x [0, 20] box, h = 2, c = 1e-4: GPU with
+    # its own stencils and weights vs the oracle end to end, and vs eq. 22
+    _announce(f"periodic pulse {mode}")
+    w = configs.periodic_pulse(h=2.0, Ly=20.0, mode=mode)
+    s = Solver.from_workload(w, precision="f64")
+    st = s.state(w.E0, w.H0)
+    s.step(st, w.steps)
+    oh, oe = osetup.operators(w)
+    Eo, Ho, _, _ = osetup.run_workload(w, oh, oe)
+    E, H = s.E_original(st), s.H_original(st)
+    e = max(ostep.rel_l2(E, Eo), ostep.rel_l2(H, Ho))
+    Ea, Ha = fields.periodic_plane_pulse(w.xyz, w.steps * w.dt, (w.steps - 0.5) * w.dt, L=200.0, sigma=30.0)
+    eE, eH = ostep.linf_errors(E, H, Ea, Ha)
+    _announce(f"  vs oracle {e:.2e}; vs eq. 22: E {eE:.2e} H {eH:.2e}")
+    assert e < 1e-10
+    assert eE < 5e-4 and eH < 5e-4
