@@ -454,6 +454,50 @@ __device__ __forceinline__ int pos4(const uint4& v, int half, int u) {
     return (int)((u & 1) ? (w >> 16) : (w & 0xFFFFu));
 }
 
+template <typename TW>
+__device__ __forceinline__ void copy4(TW (&d)[4], const TW (&s)[4]) {
+    d[0] = s[0];
+    d[1] = s[1];
+    d[2] = s[2];
+    d[3] = s[3];
+}
+// weights of chunk q of a 2D block (left unchanged past the chunk counts)
+template <typename TW>
+__device__ __forceinline__ void load2(const TW* pc, const TW* ph, int q, int C4, int V4, TW (&x)[4], TW (&y)[4],
+                                      TW (&h)[4]) {
+    if (q < C4) {
+        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, x);
+        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, y);
+    }
+    if (q < V4) ldw4(ph + q * RBFFD_TILE * 4, h);
+}
+
+// weights of chunk q of a 3D block (left unchanged past the chunk counts)
+template <typename TW>
+__device__ __forceinline__ void load3(const TW* pc, const TW* ph, int q, int C4, int V4, TW (&x)[4], TW (&y)[4],
+                                      TW (&z)[4], TW (&h)[4]) {
+    if (q < C4) {
+        ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, x);
+        ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, y);
+        ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, z);
+    }
+    if (q < V4) ldw4(ph + q * RBFFD_TILE * 4, h);
+}
+
+// 3-vector LDS entries, packed (12 B in FP32) so that more workgroups fit
+template <typename TC>
+__device__ __forceinline__ void st_lds3(TC* p, const TC (&v)[3]) {
+    p[0] = v[0];
+    p[1] = v[1];
+    p[2] = v[2];
+}
+template <typename TC>
+__device__ __forceinline__ void ld_lds3(const TC* p, TC (&v)[3]) {
+    v[0] = p[0];
+    v[1] = p[1];
+    v[2] = p[2];
+}
+
 // one 16-byte (FP32) or two 16-byte (FP64) LDS accesses per 3-vector entry
 __device__ __forceinline__ void st_lds4(float* p, const float (&v)[3]) {
     *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], 0.0f);
@@ -525,45 +569,33 @@ __global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
     const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + lane;
     const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
     const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
-    const int qb = min(a.C4, a.V4), qm = max(a.C4, a.V4);
-    uint4 li = make_uint4(0, 0, 0, 0);
+    const int qm = max(a.C4, a.V4);
+    // chunk q + 1 is loaded while chunk q is summed
+    uint4 li = ldu4s(pl);
+    TW nx[4] = {0, 0, 0, 0}, ny[4] = {0, 0, 0, 0}, nh[4] = {0, 0, 0, 0};
+    load2(pc, ph, 0, a.C4, a.V4, nx, ny, nh);
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) li = ldu4s(pl + (q >> 1) * RBFFD_TILE);
+        const uint4 lc = li;
+        TW wx[4], wy[4], wh[4];
+        copy4(wx, nx); copy4(wy, ny); copy4(wh, nh);
+        if (q + 1 < qm) {
+            if (((q + 1) & 1) == 0) li = ldu4s(pl + ((q + 1) >> 1) * RBFFD_TILE);
+            load2(pc, ph, q + 1, a.C4, a.V4, nx, ny, nh);
+        }
         const int hf = q & 1;
-        if (q < qb) {
-            TW wx[4], wy[4], wh[4];
-            ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-            ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
-            ldw4(ph + q * RBFFD_TILE * 4, wh);
+        if (q < a.C4) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int k = pos4(li, hf, u);
-                const TC de = sE[k] - e0;
-                dx += (TC)wx[u] * de;
-                dy += (TC)wy[u] * de;
-                TC hx, hy;
-                ld_lds2(sH + 2 * k, hx, hy);
-                vx += (TC)wh[u] * (hx - hx0);
-                vy += (TC)wh[u] * (hy - hy0);
-            }
-        } else if (q < a.C4) {
-            TW wx[4], wy[4];
-            ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-            ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const TC de = sE[pos4(li, hf, u)] - e0;
+                const TC de = sE[pos4(lc, hf, u)] - e0;
                 dx += (TC)wx[u] * de;
                 dy += (TC)wy[u] * de;
             }
-        } else {
-            TW wh[4];
-            ldw4(ph + q * RBFFD_TILE * 4, wh);
+        }
+        if (q < a.V4) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int k = pos4(li, hf, u);
                 TC hx, hy;
-                ld_lds2(sH + 2 * k, hx, hy);
+                ld_lds2(sH + 2 * pos4(lc, hf, u), hx, hy);
                 vx += (TC)wh[u] * (hx - hx0);
                 vy += (TC)wh[u] * (hy - hy0);
             }
@@ -603,40 +635,30 @@ __global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
     const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + lane;
     const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
     const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
-    const int qb = min(a.C4, a.V4), qm = max(a.C4, a.V4);
-    uint4 li = make_uint4(0, 0, 0, 0);
+    const int qm = max(a.C4, a.V4);
+    uint4 li = ldu4s(pl);
+    TW nx[4] = {0, 0, 0, 0}, ny[4] = {0, 0, 0, 0}, nh[4] = {0, 0, 0, 0};
+    load2(pc, ph, 0, a.C4, a.V4, nx, ny, nh);
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) li = ldu4s(pl + (q >> 1) * RBFFD_TILE);
+        const uint4 lc = li;
+        TW wx[4], wy[4], wh[4];
+        copy4(wx, nx); copy4(wy, ny); copy4(wh, nh);
+        if (q + 1 < qm) {
+            if (((q + 1) & 1) == 0) li = ldu4s(pl + ((q + 1) >> 1) * RBFFD_TILE);
+            load2(pc, ph, q + 1, a.C4, a.V4, nx, ny, nh);
+        }
         const int hf = q & 1;
-        if (q < qb) {
-            TW wx[4], wy[4], wh[4];
-            ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-            ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
-            ldw4(ph + q * RBFFD_TILE * 4, wh);
+        if (q < a.C4) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int k = pos4(li, hf, u);
                 TC hx, hy;
-                ld_lds2(sH + 2 * k, hx, hy);
-                cu += (TC)wx[u] * (hy - hy0) - (TC)wy[u] * (hx - hx0);
-                ve += (TC)wh[u] * (sE[k] - e0);
-            }
-        } else if (q < a.C4) {
-            TW wx[4], wy[4];
-            ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-            ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = pos4(li, hf, u);
-                TC hx, hy;
-                ld_lds2(sH + 2 * k, hx, hy);
+                ld_lds2(sH + 2 * pos4(lc, hf, u), hx, hy);
                 cu += (TC)wx[u] * (hy - hy0) - (TC)wy[u] * (hx - hx0);
             }
-        } else {
-            TW wh[4];
-            ldw4(ph + q * RBFFD_TILE * 4, wh);
+        }
+        if (q < a.V4) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) ve += (TC)wh[u] * (sE[pos4(li, hf, u)] - e0);
+            for (int u = 0; u < 4; ++u) ve += (TC)wh[u] * (sE[pos4(lc, hf, u)] - e0);
         }
     }
     if (i < a.N) {
@@ -650,8 +672,8 @@ template <typename TS, typename TW>
 __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
-    TC* sE = lds_base<TC>();                           // 4 values per entry
-    TC* sH = sE + 4 * (int64_t)a.hmax;
+    TC* sE = lds_base<TC>();                           // 3 values per entry
+    TC* sH = sE + 3 * (int64_t)a.hmax;
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
     for (int k = threadIdx.x; k < hc; k += blockDim.x) {
@@ -659,8 +681,8 @@ __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
         TC e[3], hh[3];
         S::ld3(a.E, j, e[0], e[1], e[2]);
         S::ld3(a.H, j, hh[0], hh[1], hh[2]);
-        st_lds4(sE + 4 * k, e);
-        st_lds4(sH + 4 * k, hh);
+        st_lds3(sE + 3 * k, e);
+        st_lds3(sH + 3 * k, hh);
     }
     __syncthreads();
     const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
@@ -676,20 +698,25 @@ __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
     const TW* pc = a.wc + (tile * a.C4 * 3 * RBFFD_TILE + lane) * 4;
     const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
     const int qm = max(a.C4, a.V4);
-    uint4 li = make_uint4(0, 0, 0, 0);
+    // chunk q + 1 is loaded while chunk q is summed
+    uint4 li = ldu4s(pl);
+    TW nx[4] = {0, 0, 0, 0}, ny[4] = {0, 0, 0, 0}, nz[4] = {0, 0, 0, 0}, nh[4] = {0, 0, 0, 0};
+    load3(pc, ph, 0, a.C4, a.V4, nx, ny, nz, nh);
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) li = ldu4s(pl + (q >> 1) * RBFFD_TILE);
+        const uint4 lc = li;
+        TW wx[4], wy[4], wz[4], wh[4];
+        copy4(wx, nx); copy4(wy, ny); copy4(wz, nz); copy4(wh, nh);
+        if (q + 1 < qm) {
+            if (((q + 1) & 1) == 0) li = ldu4s(pl + ((q + 1) >> 1) * RBFFD_TILE);
+            load3(pc, ph, q + 1, a.C4, a.V4, nx, ny, nz, nh);
+        }
         const int hf = q & 1;
         if (q < a.C4) {
-            TW wx[4], wy[4], wz[4];
-            ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
-            ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
-            ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int k = pos4(li, hf, u);
+                const int k = pos4(lc, hf, u);
                 TC v[3];
-                ld_lds4(sE + 4 * k, v);
+                ld_lds3(sE + 3 * k, v);
                 const TC ex = v[0] - ex0, ey = v[1] - ey0, ez = v[2] - ez0;
                 xEy += (TC)wx[u] * ey; xEz += (TC)wx[u] * ez;
                 yEx += (TC)wy[u] * ex; yEz += (TC)wy[u] * ez;
@@ -697,12 +724,10 @@ __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
             }
         }
         if (q < a.V4) {
-            TW wh[4];
-            ldw4(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 TC v[3];
-                ld_lds4(sH + 4 * pos4(li, hf, u), v);
+                ld_lds3(sH + 3 * pos4(lc, hf, u), v);
                 vx += (TC)wh[u] * (v[0] - hx0);
                 vy += (TC)wh[u] * (v[1] - hy0);
                 vz += (TC)wh[u] * (v[2] - hz0);
@@ -721,7 +746,7 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
     TC* sE = lds_base<TC>();
-    TC* sH = sE + 4 * (int64_t)a.hmax;
+    TC* sH = sE + 3 * (int64_t)a.hmax;
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
     for (int k = threadIdx.x; k < hc; k += blockDim.x) {
@@ -729,8 +754,8 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
         TC e[3], hh[3];
         S::ld3(a.E, j, e[0], e[1], e[2]);
         S::ld3(a.H, j, hh[0], hh[1], hh[2]);
-        st_lds4(sE + 4 * k, e);
-        st_lds4(sH + 4 * k, hh);
+        st_lds3(sE + 3 * k, e);
+        st_lds3(sH + 3 * k, hh);
     }
     __syncthreads();
     const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
@@ -746,20 +771,24 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
     const TW* pc = a.wc + (tile * a.C4 * 3 * RBFFD_TILE + lane) * 4;
     const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
     const int qm = max(a.C4, a.V4);
-    uint4 li = make_uint4(0, 0, 0, 0);
+    uint4 li = ldu4s(pl);
+    TW nx[4] = {0, 0, 0, 0}, ny[4] = {0, 0, 0, 0}, nz[4] = {0, 0, 0, 0}, nh[4] = {0, 0, 0, 0};
+    load3(pc, ph, 0, a.C4, a.V4, nx, ny, nz, nh);
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) li = ldu4s(pl + (q >> 1) * RBFFD_TILE);
+        const uint4 lc = li;
+        TW wx[4], wy[4], wz[4], wh[4];
+        copy4(wx, nx); copy4(wy, ny); copy4(wz, nz); copy4(wh, nh);
+        if (q + 1 < qm) {
+            if (((q + 1) & 1) == 0) li = ldu4s(pl + ((q + 1) >> 1) * RBFFD_TILE);
+            load3(pc, ph, q + 1, a.C4, a.V4, nx, ny, nz, nh);
+        }
         const int hf = q & 1;
         if (q < a.C4) {
-            TW wx[4], wy[4], wz[4];
-            ldw4(pc + (q * 3 + 0) * RBFFD_TILE * 4, wx);
-            ldw4(pc + (q * 3 + 1) * RBFFD_TILE * 4, wy);
-            ldw4(pc + (q * 3 + 2) * RBFFD_TILE * 4, wz);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int k = pos4(li, hf, u);
+                const int k = pos4(lc, hf, u);
                 TC v[3];
-                ld_lds4(sH + 4 * k, v);
+                ld_lds3(sH + 3 * k, v);
                 const TC hx = v[0] - hx0, hy = v[1] - hy0, hz = v[2] - hz0;
                 xHy += (TC)wx[u] * hy; xHz += (TC)wx[u] * hz;
                 yHx += (TC)wy[u] * hx; yHz += (TC)wy[u] * hz;
@@ -767,12 +796,10 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
             }
         }
         if (q < a.V4) {
-            TW wh[4];
-            ldw4(ph + q * RBFFD_TILE * 4, wh);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 TC v[3];
-                ld_lds4(sE + 4 * pos4(li, hf, u), v);
+                ld_lds3(sE + 3 * pos4(lc, hf, u), v);
                 vx += (TC)wh[u] * (v[0] - ex0);
                 vy += (TC)wh[u] * (v[1] - ey0);
                 vz += (TC)wh[u] * (v[2] - ez0);
@@ -1001,7 +1028,7 @@ void launch_half(const rbffd_plan* p, bool hupd, const void* E, const void* H, v
             if (hupd) hipLaunchKernelGGL((k_h2l<TS, TW>), grid, block, lds, st, a);
             else hipLaunchKernelGGL((k_e2l<TS, TW>), grid, block, lds, st, a);
         } else {
-            const size_t lds = (size_t)8 * o.hmax * sizeof(TC);
+            const size_t lds = (size_t)6 * o.hmax * sizeof(TC);
             if (hupd) hipLaunchKernelGGL((k_h3l<TS, TW>), grid, block, lds, st, a);
             else hipLaunchKernelGGL((k_e3l<TS, TW>), grid, block, lds, st, a);
         }
