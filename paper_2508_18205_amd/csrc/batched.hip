@@ -115,18 +115,20 @@ __global__ __launch_bounds__(256) void k_eb(BA a) {
 }
 
 // ---- LDS-staged batch -----------------------------------------------------
-// Workgroup = one 64-node tile x one 16-field slice.  It copies the slice of
-// every halo node's rows (E, Hx, Hy) into LDS, then 4 threads per node each
-// update 4 fields; stencil positions (16-bit) and weights come from the same
-// tile-sliced packed arrays as the single-field kernels, one 16-byte load per
-// 4 slots shared by the node's 4 threads.
+// Workgroup = one 256-node tile x one 16-field slice (1024 threads).  It
+// copies the slice of every halo node's rows (E, Hx, Hy) into LDS, then 4
+// threads per node each update 4 fields; stencil positions (16-bit) and
+// weights come from the same tile-sliced packed arrays as the single-field
+// kernels (and the same halo lists), one 16-byte load per 4 slots shared by
+// the node's 4 threads.  The slices of one tile are consecutive workgroups,
+// so they meet the tile's weights in L2.
 struct BLA {
     const float* E;
     const float* H;
     float* out;
     const uint4* lidx;    // [tiles][Q8][64] x 8 u16 halo positions
     const int32_t* hpool;
-    const int32_t* hoff;  // [tiles + 1]
+    const int32_t* hoff;  // [256-node tiles + 1]
     const float* wc;      // [tiles][C4][2][64][4]
     const float* wh;      // [tiles][V4][64][4]
     int64_t N, tiles;
@@ -156,35 +158,41 @@ __device__ __forceinline__ int posq(const uint4& v, int half, int u) {
     return (int)((u & 1) ? (w >> 16) : (w & 0xFFFFu));
 }
 
+template <int KSL>
 __device__ __forceinline__ void stage_slice(const BLA& a, float* sm, int64_t tile, int ks) {
     const int h0 = a.hoff[tile], hc = a.hoff[tile + 1] - h0;
     const int64_t K = a.K;
-    const int kof = ks * RBFFD_KSLICE;
-    for (int it = threadIdx.x; it < hc * 12; it += blockDim.x) {
-        const int k = it / 12, r = it - k * 12, c = r >> 2, q = r & 3;
+    const int kof = ks * KSL;
+    constexpr int Q = KSL / 4;            // 16-byte pieces per row slice
+    for (int it = threadIdx.x; it < hc * 3 * Q; it += blockDim.x) {
+        const int k = it / (3 * Q), r = it - k * (3 * Q), c = r / Q, q = r - c * Q;
         const int64_t j = a.hpool[h0 + k];
         const float* src = c == 0 ? a.E + j * K : a.H + (j * 2 + (c - 1)) * K;
-        stf4(sm + (k * 3 + c) * RBFFD_KSLICE + q * 4, ldf4(src + kof + q * 4));
+        stf4(sm + (k * 3 + c) * KSL + q * 4, ldf4(src + kof + q * 4));
     }
 }
 
-__global__ __launch_bounds__(256) void k_hbl(BLA a) {
+template <int TPN>
+__global__ __launch_bounds__(RBFFD_WGT * TPN) void k_hbl(BLA a) {
+    constexpr int KSL = 4 * TPN;          // fields per slice, 4 per thread
     extern __shared__ __align__(16) float sm[];
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int64_t tile = wg / a.KS;
     const int ks = wg % a.KS;
-    stage_slice(a, sm, tile, ks);
+    stage_slice<KSL>(a, sm, tile, ks);
     __syncthreads();
-    const int nl = threadIdx.x >> 2, fq = threadIdx.x & 3;
-    const int64_t i = tile * RBFFD_TILE + nl;
+    const int nl = threadIdx.x / TPN, fq = threadIdx.x % TPN;
+    const int64_t i = tile * RBFFD_WGT + nl;
     if (i >= a.N) return;
+    const int64_t t64 = i / RBFFD_TILE;
+    const int ln = (int)(i % RBFFD_TILE);
     const int64_t K = a.K;
-    const int k0 = ks * RBFFD_KSLICE + fq * 4;
+    const int k0 = ks * KSL + fq * 4;
     const f4 e0 = ldf4(a.E + i * K + k0), hx0 = ldf4(a.H + (i * 2) * K + k0), hy0 = ldf4(a.H + (i * 2 + 1) * K + k0);
     f4 dx{0, 0, 0, 0}, dy{0, 0, 0, 0}, vx{0, 0, 0, 0}, vy{0, 0, 0, 0};
-    const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + nl;
-    const float* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + nl) * 4;
-    const float* ph = a.wh + (tile * a.V4 * RBFFD_TILE + nl) * 4;
+    const uint4* pl = a.lidx + t64 * a.Q8 * RBFFD_TILE + ln;
+    const float* pc = a.wc + (t64 * a.C4 * 2 * RBFFD_TILE + ln) * 4;
+    const float* ph = a.wh + (t64 * a.V4 * RBFFD_TILE + ln) * 4;
     const int qm = max(a.C4, a.V4);
     uint4 li = make_uint4(0, 0, 0, 0);
     for (int q = 0; q < qm; ++q) {
@@ -195,7 +203,7 @@ __global__ __launch_bounds__(256) void k_hbl(BLA a) {
             const float wxs[4] = {wx.x, wx.y, wx.z, wx.w}, wys[4] = {wy.x, wy.y, wy.z, wy.w};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const f4 e = ldf4(sm + (posq(li, hf, u) * 3 + 0) * RBFFD_KSLICE + fq * 4);
+                const f4 e = ldf4(sm + (posq(li, hf, u) * 3 + 0) * KSL + fq * 4);
                 fma4(dx, wxs[u], e, e0);
                 fma4(dy, wys[u], e, e0);
             }
@@ -206,8 +214,8 @@ __global__ __launch_bounds__(256) void k_hbl(BLA a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = posq(li, hf, u);
-                fma4(vx, whs[u], ldf4(sm + (k * 3 + 1) * RBFFD_KSLICE + fq * 4), hx0);
-                fma4(vy, whs[u], ldf4(sm + (k * 3 + 2) * RBFFD_KSLICE + fq * 4), hy0);
+                fma4(vx, whs[u], ldf4(sm + (k * 3 + 1) * KSL + fq * 4), hx0);
+                fma4(vy, whs[u], ldf4(sm + (k * 3 + 2) * KSL + fq * 4), hy0);
             }
         }
     }
@@ -218,23 +226,27 @@ __global__ __launch_bounds__(256) void k_hbl(BLA a) {
                                         hy0.z + A * (dx.z + G * vy.z), hy0.w + A * (dx.w + G * vy.w)});
 }
 
-__global__ __launch_bounds__(256) void k_ebl(BLA a) {
+template <int TPN>
+__global__ __launch_bounds__(RBFFD_WGT * TPN) void k_ebl(BLA a) {
+    constexpr int KSL = 4 * TPN;          // fields per slice, 4 per thread
     extern __shared__ __align__(16) float sm[];
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int64_t tile = wg / a.KS;
     const int ks = wg % a.KS;
-    stage_slice(a, sm, tile, ks);
+    stage_slice<KSL>(a, sm, tile, ks);
     __syncthreads();
-    const int nl = threadIdx.x >> 2, fq = threadIdx.x & 3;
-    const int64_t i = tile * RBFFD_TILE + nl;
+    const int nl = threadIdx.x / TPN, fq = threadIdx.x % TPN;
+    const int64_t i = tile * RBFFD_WGT + nl;
     if (i >= a.N) return;
+    const int64_t t64 = i / RBFFD_TILE;
+    const int ln = (int)(i % RBFFD_TILE);
     const int64_t K = a.K;
-    const int k0 = ks * RBFFD_KSLICE + fq * 4;
+    const int k0 = ks * KSL + fq * 4;
     const f4 e0 = ldf4(a.E + i * K + k0), hx0 = ldf4(a.H + (i * 2) * K + k0), hy0 = ldf4(a.H + (i * 2 + 1) * K + k0);
     f4 cu{0, 0, 0, 0}, ve{0, 0, 0, 0};
-    const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + nl;
-    const float* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + nl) * 4;
-    const float* ph = a.wh + (tile * a.V4 * RBFFD_TILE + nl) * 4;
+    const uint4* pl = a.lidx + t64 * a.Q8 * RBFFD_TILE + ln;
+    const float* pc = a.wc + (t64 * a.C4 * 2 * RBFFD_TILE + ln) * 4;
+    const float* ph = a.wh + (t64 * a.V4 * RBFFD_TILE + ln) * 4;
     const int qm = max(a.C4, a.V4);
     uint4 li = make_uint4(0, 0, 0, 0);
     for (int q = 0; q < qm; ++q) {
@@ -247,8 +259,8 @@ __global__ __launch_bounds__(256) void k_ebl(BLA a) {
             for (int u = 0; u < 4; ++u) {
                 const int k = posq(li, hf, u);
                 // curl H = D^dx Hy - D^dy Hx, in the single-field kernels' order
-                const f4 hx = ldf4(sm + (k * 3 + 1) * RBFFD_KSLICE + fq * 4);
-                const f4 hy = ldf4(sm + (k * 3 + 2) * RBFFD_KSLICE + fq * 4);
+                const f4 hx = ldf4(sm + (k * 3 + 1) * KSL + fq * 4);
+                const f4 hy = ldf4(sm + (k * 3 + 2) * KSL + fq * 4);
                 cu.x += wxs[u] * (hy.x - hy0.x) - wys[u] * (hx.x - hx0.x);
                 cu.y += wxs[u] * (hy.y - hy0.y) - wys[u] * (hx.y - hx0.y);
                 cu.z += wxs[u] * (hy.z - hy0.z) - wys[u] * (hx.z - hx0.z);
@@ -260,7 +272,7 @@ __global__ __launch_bounds__(256) void k_ebl(BLA a) {
             const float whs[4] = {wh.x, wh.y, wh.z, wh.w};
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                fma4(ve, whs[u], ldf4(sm + (posq(li, hf, u) * 3 + 0) * RBFFD_KSLICE + fq * 4), e0);
+                fma4(ve, whs[u], ldf4(sm + (posq(li, hf, u) * 3 + 0) * KSL + fq * 4), e0);
         }
     }
     const float A = a.a, G = a.g;
@@ -287,13 +299,23 @@ BA make_args(const rbffd_plan* p) {
     return a;
 }
 
-bool staged(const rbffd_plan* p) {
-    return p->var.lds && p->opH.hmax > 0 && (p->K % RBFFD_KSLICE) == 0;
+// slice width: 16 fields (4 threads per node) when the tile's halo slice fits
+// the LDS budget and the variant asks for it, else 8 (2 threads per node)
+int slice_tpn(const rbffd_plan* p) {
+    if (!p->var.lds || p->opH.hmax <= 0) return 0;
+    const int64_t per16 = (int64_t)3 * 16 * 4;
+    if (p->var.persist >= 16 && p->K % 16 == 0 && p->opH.hmax * per16 <= RBFFD_LDS_BUDGET_BATCH) return 4;
+    if (p->K % 8 == 0) return 2;
+    return 0;
 }
+
+bool staged(const rbffd_plan* p) { return slice_tpn(p) > 0; }
 
 void launch_pair_staged(const rbffd_plan* p, const rbffd_fields* f, int c, hipStream_t st) {
     const int o = 1 - c;
     const OpBlock& ob = p->opH;
+    const int tpn = slice_tpn(p);
+    const int ksl = 4 * tpn;
     BLA a{};
     a.lidx = (const uint4*)ob.lidx;
     a.hpool = ob.hpool;
@@ -303,24 +325,26 @@ void launch_pair_staged(const rbffd_plan* p, const rbffd_fields* f, int c, hipSt
     a.N = ob.Nt;
     a.tiles = ob.tiles;
     a.K = p->K;
-    a.KS = p->K / RBFFD_KSLICE;
+    a.KS = p->K / ksl;
     a.C4 = ob.C4;
     a.V4 = ob.V4;
     a.Q8 = ob.Q8;
     a.xcd = p->var.xcd;
     a.g = (float)p->gamma;
     a.emask = p->E.emask;
-    const dim3 grid((unsigned)(ob.tiles * a.KS)), block(256);
-    const size_t lds = (size_t)ob.hmax * 3 * RBFFD_KSLICE * sizeof(float);
+    const dim3 grid((unsigned)(ob.nwg * a.KS)), block(RBFFD_WGT * tpn);
+    const size_t lds = (size_t)ob.hmax * 3 * ksl * sizeof(float);
     a.E = (const float*)f->E[c];
     a.H = (const float*)f->H[c];
     a.out = (float*)f->H[o];
     a.a = (float)(p->dt / p->p.mu0);
-    hipLaunchKernelGGL(k_hbl, grid, block, lds, st, a);
+    if (tpn == 4) hipLaunchKernelGGL(k_hbl<4>, grid, block, lds, st, a);
+    else hipLaunchKernelGGL(k_hbl<2>, grid, block, lds, st, a);
     a.H = (const float*)f->H[o];
     a.out = (float*)f->E[o];
     a.a = (float)(p->dt / p->p.eps0);
-    hipLaunchKernelGGL(k_ebl, grid, block, lds, st, a);
+    if (tpn == 4) hipLaunchKernelGGL(k_ebl<4>, grid, block, lds, st, a);
+    else hipLaunchKernelGGL(k_ebl<2>, grid, block, lds, st, a);
 }
 
 void launch_pair(const rbffd_plan* p, const rbffd_fields* f, int c, hipStream_t st) {

@@ -90,10 +90,9 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int K, bool adjoint) {
     if (!o.cross) {
         o.st_union = b.take<int32_t>(o.Nt * o.ns);
         o.pidx = b.take_bytes(T * o.S4 * 16);
-        // halo lists: 256-node workgroup tiles for the single-field kernels,
-        // 64-node tiles (node-major positions) for the K-field batch
+        // halo lists of 256-node workgroup tiles (single field and K-field batch)
         o.Q8 = (int)cdiv(o.ns - 1, 8);
-        o.nwg = K == 1 ? cdiv(o.tiles, RBFFD_WGT / RBFFD_TILE) : o.tiles;
+        o.nwg = cdiv(o.tiles, RBFFD_WGT / RBFFD_TILE);
         o.lidx = b.take<uint16_t>(T * o.Q8 * 8);
         o.hpool = b.take<int32_t>(o.Nt * o.ns);
         o.hoff = b.take<int32_t>(o.nwg + 1);

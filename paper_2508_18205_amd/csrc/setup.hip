@@ -1188,7 +1188,7 @@ int build_halos(rbffd_plan* p, void* wsp, hipStream_t st) {
     void* temp = w.take<char>((int64_t)tb);
     void* stemp = w.take<char>((int64_t)sb);
     const bool batch = p->K > 1;
-    const int tsz = batch ? RBFFD_TILE : RBFFD_WGT;
+    const int tsz = RBFFD_WGT;
     hipLaunchKernelGGL(k_hkeys, dim3(blocks(E)), dim3(256), 0, st, o.st_union, N, (int)ns, tsz, kin);
     int end_bit = 32;
     while (end_bit < 64 && ((uint64_t)1 << (end_bit - 32)) <= (uint64_t)o.nwg) ++end_bit;
@@ -1207,7 +1207,7 @@ int build_halos(rbffd_plan* p, void* wsp, hipStream_t st) {
     // staging only when a workgroup's list fits the LDS budget and 16-bit positions
     const int fb = field_elem_bytes(p->p.fdtype) == 8 ? 8 : 4;
     // single field: one value per component; batch: a 16-field slice per component
-    const int64_t per = batch ? (int64_t)(p->fe_comp + p->fh_comp) * RBFFD_KSLICE * 4 : (int64_t)(p->FE + p->FH) * fb;
+    const int64_t per = batch ? (int64_t)(p->fe_comp + p->fh_comp) * 8 * 4 : (int64_t)(p->FE + p->FH) * fb;
     const int64_t budget = batch ? RBFFD_LDS_BUDGET_BATCH : RBFFD_LDS_BUDGET;
     o.hmax = (mx < 65536 && (int64_t)mx * per <= budget) ? mx : 0;
     p->opE = p->opH;

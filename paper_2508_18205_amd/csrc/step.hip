@@ -1302,8 +1302,14 @@ extern "C" int rbffd_autotune(rbffd_plan* p, rbffd_fields* f, int32_t reps, void
             for (int x : {0, 1}) cand.push_back(Variant{b, x, 8, 0});
         }
     }
-    if (staged)
-        for (int x : {0, 1}) cand.push_back(Variant{256, x, 8, 1});
+    if (staged) {
+        if (p->K > 1) {
+            // staged batch: 8-field slices (persist < 16) or 16-field slices
+            for (int pe : {8, 16}) cand.push_back(Variant{256, 1, pe, 1});
+        } else {
+            for (int x : {0, 1}) cand.push_back(Variant{256, x, 8, 1});
+        }
+    }
     Variant best = p->var;
     float best_ms = 1e30f;
     hipEvent_t e0, e1;
