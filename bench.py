@@ -118,7 +118,9 @@ def main():
     ap.add_argument("--accuracy-steps", type=int, default=10000)
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip FP64, accuracy and batched legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip every leg after the headline one")
+    ap.add_argument("--legs", default="fp64,accuracy,batched,accuracy_alpha2,bf16,3d",
+                    help="comma-separated extra legs to run after the headline measurement")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter scaling)")
@@ -211,7 +213,8 @@ def main():
                            "avg_launch_us": round((te if dominant == "H" else th) * 1e6, 2)}}
 
     extras = {}
-    if not args.no_extras:
+    legs = set() if args.no_extras else set(x for x in args.legs.split(",") if x)
+    if legs & {"fp64", "accuracy"}:
         # FP64 rate on the same nodes, and FP32 vs FP64 after the workload's steps
         s64, t64 = setup("f64")
         st64 = s64.state(w.E0, w.H0)
@@ -240,6 +243,8 @@ def main():
         log(f"accuracy after {T} steps: {extras['accuracy']}")
         del s64, st64, a64
         torch.cuda.empty_cache()
+    T = args.accuracy_steps
+    if "batched" in legs:
         # K = 64 fields sharing one weight set (250k-node jittered grid)
         wb = configs.batched_2d(scale=1.0, K=64)
         sb = Solver.from_workload(wb, precision="f32", K=64)
@@ -262,12 +267,13 @@ def main():
         log(f"batched: {extras['batched']}")
         del sb, stb
         torch.cuda.empty_cache()
+    if "accuracy_alpha2" in legs:
         # the same nodes and curl stencils with alpha = 2 (c*dt = 3e-3), which is
         # stable at this size: FP32 vs FP64 after 10^4 steps
         ws = configs.Workload(w.name, w.dim, w.xyz, w.flags, w.h, w.n, w.m, 2, 31, 3e-3, T)
         ws.E0, ws.H0 = w.E0, w.H0
         acc = {}
-        for prec in ("f32", "f64"):
+        for prec in ("f32", "f64", "bf16"):
             sv = Solver.from_workload(ws, precision=prec)
             sa = sv.state(ws.E0, ws.H0)
             r = sv.run(sa, T, energy_every=max(1, T // 20), use_graph=True)
@@ -279,8 +285,26 @@ def main():
             "steps": T, "alpha": 2, "n_hv": 31, "chat": 3e-3,
             "fp32_vs_fp64_rel_l2_E": rl2(acc["f32"][0], acc["f64"][0]),
             "fp32_vs_fp64_rel_l2_H": rl2(acc["f32"][1], acc["f64"][1]),
+            "bf16_vs_fp64_rel_l2_E": rl2(acc["bf16"][0], acc["f64"][0]),
+            "bf16_vs_fp64_rel_l2_H": rl2(acc["bf16"][1], acc["f64"][1]),
             "fp64_energy_ratio_min": float(u.min()), "fp64_energy_ratio_max": float(u.max())}
         log(f"accuracy (alpha=2 variant): {extras['accuracy_alpha2']}")
+    if "bf16" in legs:
+        # BF16 field storage (FP32 weights and arithmetic) on the headline workload
+        sbf, tbf = setup("bf16")
+        abf = sbf.state(w.E0, w.H0)
+        sbf.run(abf, args.warmup, use_graph=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        sbf.run(abf, args.steps, use_graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        extras["bf16_storage"] = {"value": w.N * args.steps / (e0.elapsed_time(e1) * 1e-3), "unit": "node-steps/s",
+                                  "note": "accuracy in accuracy_alpha2 (BF16 updates below the BF16 ulp stagnate)"}
+        log(f"bf16: {extras['bf16_storage']}")
+        del sbf, abf
+        torch.cuda.empty_cache()
+    if "3d" in legs:
         # 3D cube, 8.0M nodes, FP32 rate and FP32 vs FP64 over the workload's 2000 steps
         w3 = configs.tm111_3d(scale=1.0, chat=1e-3)
         r3 = {}
