@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip every leg after the headline one")
-    ap.add_argument("--legs", default="fp64,accuracy,batched,accuracy_alpha2,bf16,3d",
+    ap.add_argument("--legs", default="fp64,accuracy,batched,accuracy_alpha2,bf16,adjoint,stag2,3d",
                     help="comma-separated extra legs to run after the headline measurement")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -303,6 +303,82 @@ def main():
                                   "note": "accuracy in accuracy_alpha2 (BF16 updates below the BF16 ulp stagnate)"}
         log(f"bf16: {extras['bf16_storage']}")
         del sbf, abf
+        torch.cuda.empty_cache()
+    if "adjoint" in legs:
+        # 250k-node adjoint workload: FP32 forward with sqrt(T) checkpoints and
+        # the discrete adjoint; FP64 gradient checked by central differences
+        wa = configs.adjoint_2d(scale=1.0, chat=1e-3)
+        d_res = {}
+        for prec in ("f32", "f64"):
+            sa = Solver.from_workload(wa, precision=prec, adjoint=True)
+            src = (wa.src_node, wa.src_amp, wa.src_wave)
+            C = int(math.ceil(math.sqrt(wa.steps)))
+            st0 = sa.state(np.zeros((wa.N, 1)), np.zeros((wa.N, 2)), eps_r=np.ones(wa.N))
+            dat = sa.run(st0, wa.steps, src=src, rcv=wa.rcv_node)["traces"].clone()
+            stf = sa.state(np.zeros((wa.N, 1)), np.zeros((wa.N, 2)), eps_r=wa.eps_r)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            out = sa.run(stf, wa.steps, src=src, rcv=wa.rcv_node, ckpt_every=C)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t_fwd = e0.elapsed_time(e1) * 1e-3
+            gt = out["traces"] - dat
+            e0.record(stream)
+            g_eps, g_amp = sa.adjoint(stf, wa.steps, out["ckpt"], C, gt, src=src, rcv=wa.rcv_node)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t_adj = e0.elapsed_time(e1) * 1e-3
+            d_res[prec] = dict(t_fwd=t_fwd, t_adj=t_adj, g=g_eps, a=g_amp)
+            if prec == "f64":
+                rng = np.random.default_rng(7)
+                v = rng.uniform(-1, 1, wa.N)
+                hh = 1e-6
+
+                def J(e):
+                    stj = sa.state(np.zeros((wa.N, 1)), np.zeros((wa.N, 2)), eps_r=e)
+                    r = sa.run(stj, wa.steps, src=src, rcv=wa.rcv_node)["traces"] - dat
+                    return 0.5 * float((r * r).sum())
+
+                fd = (J(wa.eps_r + hh * v) - J(wa.eps_r - hh * v)) / (2 * hh)
+                an = float((g_eps * v).sum())
+                d_res["fd"] = (fd, an)
+            del sa, st0, stf, out
+            torch.cuda.empty_cache()
+        fd, an = d_res["fd"]
+        g32, g64 = d_res["f32"]["g"], d_res["f64"]["g"]
+        extras["adjoint"] = {
+            "N": wa.N, "steps": wa.steps, "receivers": len(wa.rcv_node), "ckpt_every": int(math.ceil(math.sqrt(wa.steps))),
+            "forward_ms_f32": round(d_res["f32"]["t_fwd"] * 1e3, 2), "adjoint_ms_f32": round(d_res["f32"]["t_adj"] * 1e3, 2),
+            "gradient_node_steps_per_s_f32": wa.N * wa.steps / (d_res["f32"]["t_fwd"] + d_res["f32"]["t_adj"]),
+            "forward_ms_f64": round(d_res["f64"]["t_fwd"] * 1e3, 2), "adjoint_ms_f64": round(d_res["f64"]["t_adj"] * 1e3, 2),
+            "fd_check_f64": {"central_difference": fd, "adjoint": an, "rel_diff": abs(fd - an) / abs(an)},
+            "grad_eps_f32_vs_f64_rel": float(np.abs(g32 - g64).max() / np.abs(g64).max()),
+            "grad_amp_f32_vs_f64_rel": float(np.abs(d_res["f32"]["a"] - d_res["f64"]["a"]).max()
+                                             / np.abs(d_res["f64"]["a"]).max())}
+        log(f"adjoint: {extras['adjoint']}")
+    if "stag2" in legs:
+        # two node sets (E on a 1000^2 jittered grid, H on its 999^2 cell centres)
+        from synth import nodes as _nodes
+        xe, fe_, he = _nodes.jittered_grid((1000, 1000), seed=8)
+        xh, fh_, hh_ = _nodes.dual_grid_2d(999, seed=8)
+        w2 = configs.Workload("stag2", 2, xe, fe_, he, 12, 2, 2, 31, 1e-3, 100, mode="STAG2")
+        w2.xyz_h, w2.flags_h, w2.h_h = xh, fh_, hh_
+        w2.E0 = np.zeros((w2.N, 1))
+        w2.H0 = np.zeros((xh.shape[0], 2))
+        s2 = Solver.from_workload(w2, precision="f32")
+        a2 = s2.state(w2.E0, w2.H0)
+        s2.run(a2, 10, use_graph=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        s2.run(a2, 200, use_graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t2 = e0.elapsed_time(e1) * 1e-3
+        extras["two_set"] = {"N_E": w2.N, "N_H": int(xh.shape[0]), "n": 12, "n_hv": 31,
+                             "node_steps_per_s": (w2.N + xh.shape[0]) / 2 * 200 / t2,
+                             "ms_per_step": t2 / 200 * 1e3}
+        log(f"two-set: {extras['two_set']}")
+        del s2, a2
         torch.cuda.empty_cache()
     if "3d" in legs:
         # 3D cube, 8.0M nodes, FP32 rate and FP32 vs FP64 over the workload's 2000 steps
