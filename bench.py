@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip every leg after the headline one")
-    ap.add_argument("--legs", default="fp64,accuracy,batched,accuracy_alpha2,bf16,adjoint,stag2,3d",
+    ap.add_argument("--legs", default="fp64,accuracy,batched,accuracy_alpha2,bf16,adjoint,stag2,hv_scan,3d",
                     help="comma-separated extra legs to run after the headline measurement")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -151,6 +151,16 @@ def main():
 
     def setup(prec):
         return setup_w(w, prec)
+
+    def finite_or_null(o):
+        # strict JSON has no NaN/Infinity: a diverged run reports null
+        if isinstance(o, dict):
+            return {k: finite_or_null(v) for k, v in o.items()}
+        if isinstance(o, (list, tuple)):
+            return [finite_or_null(v) for v in o]
+        if isinstance(o, float) and not math.isfinite(o):
+            return None
+        return o
 
     def rl2(x, y):
         ny = np.linalg.norm(y)
@@ -211,6 +221,30 @@ def main():
             "avg_launch_us": round((th if dominant == "H" else te) * 1e6, 2),
             "other_half": {"achieved": round(gbs_e if dominant == "H" else gbs_h, 1),
                            "avg_launch_us": round((te if dominant == "H" else th) * 1e6, 2)}}
+    if traffic:
+        # the staged kernels read 16-bit halo positions instead of the int32
+        # indices the algorithmic count assumes: the counted rate is lower
+        cgbs = traffic / (th if dominant == "H" else te) / 1e9
+        roof["counted_GBs"] = round(cgbs, 1)
+        roof["counted_frac"] = round(cgbs / HBM_PEAK_GBS, 4)
+    # measured device-copy ceiling (read + write bytes of a 2 GiB copy)
+    ca = torch.empty(1 << 29, dtype=torch.float32, device=dev)
+    cb = torch.empty_like(ca)
+    ca.fill_(1.0)
+    for _ in range(3):
+        cb.copy_(ca)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(10):
+        cb.copy_(ca)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * ca.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    roof["copy_ceiling_GBs"] = round(copy_gbs, 1)
+    roof["frac_of_copy_ceiling"] = round(ach / copy_gbs, 4)
+    del ca, cb
+    torch.cuda.empty_cache()
+    log(f"device copy ceiling: {copy_gbs:.0f} GB/s")
 
     extras = {}
     legs = set() if args.no_extras else set(x for x in args.legs.split(",") if x)
@@ -225,7 +259,8 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         v64 = w.N * args.steps / (e0.elapsed_time(e1) * 1e-3)
-        extras["fp64"] = {"value": v64, "unit": "node-steps/s", "setup_s": round(t64, 2)}
+        extras["fp64"] = {"value": v64, "unit": "node-steps/s", "setup_s": round(t64, 2),
+                          "fp32_over_fp64": round(value / v64, 3)}
         T = args.accuracy_steps
         a32 = s.state(w.E0, w.H0)
         a64 = s64.state(w.E0, w.H0)
@@ -235,11 +270,28 @@ def main():
         H32, H64 = s.H_original(a32), s64.H_original(a64)
 
         u64 = r64["energy"] / r64["energy"][0]
-        extras["accuracy"] = {
-            "steps": T, "reference": "GPU FP64 path (pinned to the FP64 oracle at 1e-12 on smaller cases)",
-            "fp32_vs_fp64_rel_l2_E": rl2(E32, E64), "fp32_vs_fp64_rel_l2_H": rl2(H32, H64),
-            "fp64_energy_ratio_max": float(np.nanmax(u64)), "fp64_energy_ratio_end": float(u64[-1]),
-            "fp64_finite": bool(np.isfinite(E64).all())}
+        every = max(1, T // 20)
+        acc1 = {"steps": T, "reference": "GPU FP64 path (pinned to the FP64 oracle at 1e-12 on smaller cases)",
+                "fp32_vs_fp64_rel_l2_E": rl2(E32, E64), "fp32_vs_fp64_rel_l2_H": rl2(H32, H64),
+                "fp64_energy_ratio_max": float(np.nanmax(u64)), "fp64_energy_ratio_end": float(u64[-1]),
+                "fp64_finite": bool(np.isfinite(E64).all())}
+        grown = np.nonzero(~(u64 <= 1.01))[0]
+        if grown.size:
+            # the configuration as specified is not energy-stable: state when the
+            # FP64 energy first left [0, 1.01] and compare the precisions up to
+            # the last sample before that
+            Tb = int(grown[0] - 1) * every
+            acc1["fp64_energy_above_1.01_at_step"] = int(grown[0]) * every
+            if Tb > 0:
+                b32 = s.state(w.E0, w.H0)
+                b64 = s64.state(w.E0, w.H0)
+                s.run(b32, Tb, use_graph=True)
+                s64.run(b64, Tb, use_graph=True)
+                acc1["bounded_steps"] = Tb
+                acc1["fp32_vs_fp64_rel_l2_E_bounded"] = rl2(s.E_original(b32), s64.E_original(b64))
+                acc1["fp32_vs_fp64_rel_l2_H_bounded"] = rl2(s.H_original(b32), s64.H_original(b64))
+                del b32, b64
+        extras["accuracy"] = acc1
         log(f"accuracy after {T} steps: {extras['accuracy']}")
         del s64, st64, a64
         torch.cuda.empty_cache()
@@ -259,13 +311,30 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         tb = e0.elapsed_time(e1) * 1e-3
+        del sb, stb
+        torch.cuda.empty_cache()
+        # one field on the same nodes and weights: 64 such runs are the alternative
+        s1 = Solver.from_workload(wb, precision="f32")
+        st1 = s1.state(wb.E0_batch[0], np.zeros((wb.N, 2)))
+        if not args.no_tune:
+            s1.autotune(st1, reps=5)
+            st1 = s1.state(wb.E0_batch[0], np.zeros((wb.N, 2)))
+        s1.run(st1, 20, use_graph=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        s1.run(st1, kb, use_graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t1 = e0.elapsed_time(e1) * 1e-3
+        del s1, st1
         extras["batched"] = {"value": wb.N * 64 * kb / tb, "unit": "field-node-steps/s", "K": 64, "N": wb.N,
+                             "single_field_node_steps_per_s": wb.N * kb / t1,
+                             "speedup_vs_64_single_runs": round(64 * t1 / tb, 2),
                              "variant": vb,
                              "steps": kb, "node_steps_per_s": wb.N * kb / tb,
                              "alg_bytes_per_field_node_step": 50.0,
                              "hbm_frac_at_50B": round(wb.N * 64 * kb / tb * 50.0 / (HBM_PEAK_GBS * 1e9), 4)}
         log(f"batched: {extras['batched']}")
-        del sb, stb
         torch.cuda.empty_cache()
     if "accuracy_alpha2" in legs:
         # the same nodes and curl stencils with alpha = 2 (c*dt = 3e-3), which is
@@ -380,6 +449,33 @@ def main():
         log(f"two-set: {extras['two_set']}")
         del s2, a2
         torch.cuda.empty_cache()
+    if "hv_scan" in legs:
+        # hyperviscosity parameter search on the 1M-node set: K = 64 values of
+        # c per round advanced together (per-field gamma, per-field energy)
+        scans = {}
+        for alpha, nhv, lo, hi, rounds in ((w.alpha, w.n_hv, 1e-8, 1e-1, 2), (2, 31, 1e-7, 1e-1, 2)):
+            ws_ = configs.Workload(w.name, w.dim, w.xyz, w.flags, w.h, w.n, w.m, alpha, nhv, 1e-3, 2000)
+            sk = Solver.from_workload(ws_, precision="f32", K=64)
+            stk = sk.state_batched(np.repeat(w.E0[None], 64, 0), np.repeat(w.H0[None], 64, 0))
+            torch.cuda.synchronize()
+            t0 = time.time()
+            r = sk.hv_scan(stk, w.E0, w.H0, lo / w.dt, hi / w.dt, rounds, 2000, 100)
+            tsc = time.time() - t0
+            acc = [float(c * w.dt) for c, o in zip(r["c"].ravel(), r["ok"].ravel()) if o]
+            scans[f"alpha{alpha}"] = {
+                "n_hv": nhv, "chat_range": [lo, hi], "K": 64, "rounds_done": int(len(r["c"])), "steps": 2000,
+                "band": [0.99, 1.01], "status": r["status"],
+                "chat_best": (r["c_best"] * w.dt) if r["c_best"] else None,
+                "chat_bracket": [r["bracket"][0] * w.dt, r["bracket"][1] * w.dt],
+                "accepted_chat_round1": [float(c * w.dt) for c, o in zip(r["c"][0], r["ok"][0]) if o],
+                "accepted_total": len(acc),
+                "umax_min_round1": float(np.min(r["umax"][0])),
+                "scan_s": round(tsc, 2),
+                "field_node_steps_per_s": w.N * 64 * 2000 * len(r["c"]) / tsc}
+            del sk, stk
+            torch.cuda.empty_cache()
+        extras["hv_scan"] = scans
+        log(f"hv scan: {scans}")
     if "3d" in legs:
         # 3D cube, 8.0M nodes, FP32 rate and FP32 vs FP64 over the workload's 2000 steps
         w3 = configs.tm111_3d(scale=1.0, chat=1e-3)
@@ -404,7 +500,8 @@ def main():
         bh3 = alg_bytes_half(w3.n, w3.n_hv, 3, sw3, 4, 3, 3, 0) * w3.N
         extras["tm111_3d"] = {
             "N": w3.N, "n": w3.n, "n_hv": w3.n_hv, "value_f32": r3["f32"]["rate"], "value_f64": r3["f64"]["rate"],
-            "unit": "node-steps/s", "setup_s_f32": round(r3["f32"]["setup"], 2),
+            "unit": "node-steps/s", "fp32_over_fp64": round(r3["f32"]["rate"] / r3["f64"]["rate"], 3),
+            "setup_s_f32": round(r3["f32"]["setup"], 2),
             "h_update_us": round(r3["f32"]["th"] * 1e6, 1), "e_update_us": round(r3["f32"]["te"] * 1e6, 1),
             "h_update_GBs": round(bh3 / r3["f32"]["th"] / 1e9, 1),
             "h_update_frac": round(bh3 / r3["f32"]["th"] / 1e9 / HBM_PEAK_GBS, 4),
@@ -431,7 +528,7 @@ def main():
         "cpu_baseline": cpu,
     }
     line.update(extras)
-    print(json.dumps(line), flush=True)
+    print(json.dumps(finite_or_null(line)), flush=True)
 
 
 if __name__ == "__main__":

@@ -133,6 +133,7 @@ typedef struct rbffd_fields {
  *  - energy_out [floor((T-1)/energy_every) + 1] double: U^n of eq. 20 for
  *    n = 0, energy_every, ... (computed inside step n from E^n and the
  *    average of H^n and H^{n+1}); NULL or energy_every = 0 disables.
+ *    K-field batch: energy_out [samples][K], one U^n per field.
  *  - soft sources: after the E bracket of step n, E (Ez in 2D) at node
  *    src_node[s] gains src_amp[s] * src_wave[n * n_src + s]; not scaled by
  *    eps_r; PEC nodes stay zero.  (2D, K = 1.)
@@ -244,6 +245,50 @@ int rbffd_run(const rbffd_plan* plan, rbffd_fields* f, const rbffd_run_args* arg
               void* workspace, void* stream);
 /* rbffd_adjoint: gradients of J(traces) (see rbffd_adjoint_args). */
 int rbffd_adjoint(const rbffd_plan* plan, const rbffd_fields* f, const rbffd_adjoint_args* args,
+                  void* stream);
+
+/* ---- hyperviscosity per field and the parameter search (Section 5.1) ------
+ * rbffd_set_field_hv (K-field batch): field k uses the hyperviscosity constant
+ * c_dev[k] (device double [K], the paper's c), i.e. gamma_k = c_k (-1)^(alpha-1)
+ * h^(2 alpha); c_dev = NULL gives every field the plan's c again.  Stays in
+ * effect for later steps and runs of the plan.
+ *
+ * rbffd_hv_scan (K-field batch, K >= 3): the paper picks c by running the
+ * problem with several c and watching the relative energy u(t) = U(t)/U(0)
+ * of eq. 20, with a bisection on c where a fine sweep is slow (Section 5.1,
+ * Figures 5-6); Section 6 accepts c when u stays in [0.99, 1.01].  Here each
+ * round runs the K fields from the same state (E0, H0), field k with
+ * c_k = lo (hi / lo)^(k / (K - 1)) over the current bracket [lo, hi]
+ * (initially [c_lo, c_hi]); c_k is accepted when every sample of u_k (every
+ * energy_every steps of T) is finite and in [u_lo, u_hi].  The next bracket is
+ * [c_{k*-1}, c_{k*}] around the smallest accepted c_{k*}.  The search stops
+ * after `rounds` rounds, or early: status 2 when no candidate of the first
+ * round is accepted (later rounds keep the previous bracket), status 1 when
+ * c_lo of a round is accepted (the edge lies below the bracket); otherwise
+ * status 0.  The field buffers are overwritten; the plan's c is restored
+ * at the end.  Synchronises the stream.  workspace: as for rbffd_run. */
+typedef struct rbffd_hv_scan_args {
+    const void* E0;          /* device [N][fe]: one field, internal order, plan type */
+    const void* H0;          /* device [N][fh]                                      */
+    double c_lo, c_hi;       /* initial bracket, 0 < c_lo < c_hi                    */
+    int32_t rounds;          /* >= 1                                                */
+    int32_t T;               /* steps per round, >= 1                               */
+    int32_t energy_every;    /* >= 1                                                */
+    int32_t reserved;
+    double u_lo, u_hi;       /* accepted band of u                                  */
+    double* c_dev;           /* device scratch [K]                                  */
+    double* energy_dev;      /* device scratch [(T-1)/energy_every + 1][K]          */
+    double* c_host;          /* host out [rounds][K] candidates (or NULL)           */
+    double* umin_host;       /* host out [rounds][K] min of u (or NULL)             */
+    double* umax_host;       /* host out [rounds][K] max of u, +inf if not finite   */
+    int32_t* ok_host;        /* host out [rounds][K] 1 = accepted (or NULL)         */
+    double c_best;           /* out: smallest accepted c, 0 if none                 */
+    double bracket[2];       /* out: final bracket                                  */
+    int32_t rounds_done;     /* out: rounds run (rows written)                      */
+    int32_t status;          /* out: 0 bracketed, 1 edge below c_lo, 2 none         */
+} rbffd_hv_scan_args;
+int rbffd_set_field_hv(rbffd_plan* plan, const double* c_dev, void* stream);
+int rbffd_hv_scan(rbffd_plan* plan, rbffd_fields* f, rbffd_hv_scan_args* args, void* workspace,
                   void* stream);
 
 /* ---- FP64 reductions (eq. 20, eq. 23) -------------------------------------

@@ -59,6 +59,16 @@ class AdjointArgs(C.Structure):
     ]
 
 
+class HvScanArgs(C.Structure):
+    _fields_ = [
+        ("E0", C.c_void_p), ("H0", C.c_void_p), ("c_lo", C.c_double), ("c_hi", C.c_double),
+        ("rounds", C.c_int32), ("T", C.c_int32), ("energy_every", C.c_int32), ("reserved", C.c_int32),
+        ("u_lo", C.c_double), ("u_hi", C.c_double), ("c_dev", C.c_void_p), ("energy_dev", C.c_void_p),
+        ("c_host", C.c_void_p), ("umin_host", C.c_void_p), ("umax_host", C.c_void_p), ("ok_host", C.c_void_p),
+        ("c_best", C.c_double), ("bracket", C.c_double * 2), ("rounds_done", C.c_int32), ("status", C.c_int32),
+    ]
+
+
 # name -> (restype, argtypes); the exported symbols of include/rbffd.h
 PROTOTYPES = {
     "rbffd_plan_create": (C.c_int, [C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
@@ -85,6 +95,8 @@ PROTOTYPES = {
     "rbffd_autotune": (C.c_int, [C.c_void_p, C.POINTER(Fields), C.c_int32, C.c_void_p]),
     "rbffd_get_variant": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "rbffd_set_variant": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "rbffd_set_field_hv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rbffd_hv_scan": (C.c_int, [C.c_void_p, C.POINTER(Fields), C.POINTER(HvScanArgs), C.c_void_p, C.c_void_p]),
 }
 
 _lib = None

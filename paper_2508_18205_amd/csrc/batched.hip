@@ -23,7 +23,8 @@ struct BA {
     int64_t N;
     int K, KC;            // fields, 64-field chunks
     int S, C, V;          // padded slot counts (multiples of 4)
-    float a, g;
+    float a;
+    const float* gk;      // per-field gamma [K]
     const uint8_t* emask;
 };
 
@@ -43,6 +44,7 @@ __global__ __launch_bounds__(256) void k_hb(BA a) {
         const int K = a.K;
         const float e0 = a.E[i * K + kk];
         const float hx0 = a.H[(i * 2 + 0) * K + kk], hy0 = a.H[(i * 2 + 1) * K + kk];
+        const float G = a.gk[kk];
         float dx = 0.f, dy = 0.f, vx = 0.f, vy = 0.f;
         const int32_t* pi = a.idx + i * a.S;
         const float* px = a.wc + (i * 2 + 0) * a.C;
@@ -70,8 +72,8 @@ __global__ __launch_bounds__(256) void k_hb(BA a) {
             vy += ph[s] * (a.H[(j * 2 + 1) * K + kk] - hy0);
         }
         if (on) {
-            a.out[(i * 2 + 0) * K + k] = hx0 + a.a * (-dy + a.g * vx);
-            a.out[(i * 2 + 1) * K + k] = hy0 + a.a * (dx + a.g * vy);
+            a.out[(i * 2 + 0) * K + k] = hx0 + a.a * (-dy + G * vx);
+            a.out[(i * 2 + 1) * K + k] = hy0 + a.a * (dx + G * vy);
         }
     }
 }
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(256) void k_eb(BA a) {
         const int K = a.K;
         const float e0 = a.E[i * K + kk];
         const float hx0 = a.H[(i * 2 + 0) * K + kk], hy0 = a.H[(i * 2 + 1) * K + kk];
+        const float G = a.gk[kk];
         float cu = 0.f, ve = 0.f;
         const int32_t* pi = a.idx + i * a.S;
         const float* px = a.wc + (i * 2 + 0) * a.C;
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(256) void k_eb(BA a) {
             const int64_t j = pi[s];
             ve += ph[s] * (a.E[j * K + kk] - e0);
         }
-        if (on) a.out[i * K + k] = (a.emask[i] & 1) ? e0 + a.a * (cu + a.g * ve) : 0.f;
+        if (on) a.out[i * K + k] = (a.emask[i] & 1) ? e0 + a.a * (cu + G * ve) : 0.f;
     }
 }
 
@@ -133,7 +136,8 @@ struct BLA {
     const float* wh;      // [tiles][V4][64][4]
     int64_t N, tiles;
     int K, KS, C4, V4, Q8, xcd;
-    float a, g;
+    float a;
+    const float* gk;      // per-field gamma [K]
     const uint8_t* emask;
 };
 
@@ -219,11 +223,12 @@ __global__ __launch_bounds__(RBFFD_WGT * TPN) void k_hbl(BLA a) {
             }
         }
     }
-    const float A = a.a, G = a.g;
-    stf4(a.out + (i * 2) * K + k0, {hx0.x + A * (-dy.x + G * vx.x), hx0.y + A * (-dy.y + G * vx.y),
-                                    hx0.z + A * (-dy.z + G * vx.z), hx0.w + A * (-dy.w + G * vx.w)});
-    stf4(a.out + (i * 2 + 1) * K + k0, {hy0.x + A * (dx.x + G * vy.x), hy0.y + A * (dx.y + G * vy.y),
-                                        hy0.z + A * (dx.z + G * vy.z), hy0.w + A * (dx.w + G * vy.w)});
+    const float A = a.a;
+    const f4 G = ldf4(a.gk + k0);
+    stf4(a.out + (i * 2) * K + k0, {hx0.x + A * (-dy.x + G.x * vx.x), hx0.y + A * (-dy.y + G.y * vx.y),
+                                    hx0.z + A * (-dy.z + G.z * vx.z), hx0.w + A * (-dy.w + G.w * vx.w)});
+    stf4(a.out + (i * 2 + 1) * K + k0, {hy0.x + A * (dx.x + G.x * vy.x), hy0.y + A * (dx.y + G.y * vy.y),
+                                        hy0.z + A * (dx.z + G.z * vy.z), hy0.w + A * (dx.w + G.w * vy.w)});
 }
 
 template <int TPN>
@@ -275,10 +280,11 @@ __global__ __launch_bounds__(RBFFD_WGT * TPN) void k_ebl(BLA a) {
                 fma4(ve, whs[u], ldf4(sm + (posq(li, hf, u) * 3 + 0) * KSL + fq * 4), e0);
         }
     }
-    const float A = a.a, G = a.g;
+    const float A = a.a;
+    const f4 G = ldf4(a.gk + k0);
     const bool keep = a.emask[i] & 1;
-    stf4(a.out + i * K + k0, keep ? f4{e0.x + A * (cu.x + G * ve.x), e0.y + A * (cu.y + G * ve.y),
-                                       e0.z + A * (cu.z + G * ve.z), e0.w + A * (cu.w + G * ve.w)}
+    stf4(a.out + i * K + k0, keep ? f4{e0.x + A * (cu.x + G.x * ve.x), e0.y + A * (cu.y + G.y * ve.y),
+                                       e0.z + A * (cu.z + G.z * ve.z), e0.w + A * (cu.w + G.w * ve.w)}
                                   : f4{0, 0, 0, 0});
 }
 
@@ -294,7 +300,7 @@ BA make_args(const rbffd_plan* p) {
     a.S = o.S4 * 4;
     a.C = o.C4 * 4;
     a.V = o.V4 * 4;
-    a.g = (float)p->gamma;
+    a.gk = p->gk;
     a.emask = p->E.emask;
     return a;
 }
@@ -311,7 +317,9 @@ int slice_tpn(const rbffd_plan* p) {
 
 bool staged(const rbffd_plan* p) { return slice_tpn(p) > 0; }
 
-void launch_pair_staged(const rbffd_plan* p, const rbffd_fields* f, int c, hipStream_t st) {
+// one half step (hupd: H update from E[c], H[c] into H[o]; else E update
+// from E[c], H[o] into E[o])
+void launch_half_staged(const rbffd_plan* p, const rbffd_fields* f, int c, bool hupd, hipStream_t st) {
     const int o = 1 - c;
     const OpBlock& ob = p->opH;
     const int tpn = slice_tpn(p);
@@ -330,25 +338,28 @@ void launch_pair_staged(const rbffd_plan* p, const rbffd_fields* f, int c, hipSt
     a.V4 = ob.V4;
     a.Q8 = ob.Q8;
     a.xcd = p->var.xcd;
-    a.g = (float)p->gamma;
+    a.gk = p->gk;
     a.emask = p->E.emask;
     const dim3 grid((unsigned)(ob.nwg * a.KS)), block(RBFFD_WGT * tpn);
     const size_t lds = (size_t)ob.hmax * 3 * ksl * sizeof(float);
     a.E = (const float*)f->E[c];
-    a.H = (const float*)f->H[c];
-    a.out = (float*)f->H[o];
-    a.a = (float)(p->dt / p->p.mu0);
-    if (tpn == 4) hipLaunchKernelGGL(k_hbl<4>, grid, block, lds, st, a);
-    else hipLaunchKernelGGL(k_hbl<2>, grid, block, lds, st, a);
-    a.H = (const float*)f->H[o];
-    a.out = (float*)f->E[o];
-    a.a = (float)(p->dt / p->p.eps0);
-    if (tpn == 4) hipLaunchKernelGGL(k_ebl<4>, grid, block, lds, st, a);
-    else hipLaunchKernelGGL(k_ebl<2>, grid, block, lds, st, a);
+    if (hupd) {
+        a.H = (const float*)f->H[c];
+        a.out = (float*)f->H[o];
+        a.a = (float)(p->dt / p->p.mu0);
+        if (tpn == 4) hipLaunchKernelGGL(k_hbl<4>, grid, block, lds, st, a);
+        else hipLaunchKernelGGL(k_hbl<2>, grid, block, lds, st, a);
+    } else {
+        a.H = (const float*)f->H[o];
+        a.out = (float*)f->E[o];
+        a.a = (float)(p->dt / p->p.eps0);
+        if (tpn == 4) hipLaunchKernelGGL(k_ebl<4>, grid, block, lds, st, a);
+        else hipLaunchKernelGGL(k_ebl<2>, grid, block, lds, st, a);
+    }
 }
 
-void launch_pair(const rbffd_plan* p, const rbffd_fields* f, int c, hipStream_t st) {
-    if (staged(p)) return launch_pair_staged(p, f, c, st);
+void launch_half(const rbffd_plan* p, const rbffd_fields* f, int c, bool hupd, hipStream_t st) {
+    if (staged(p)) return launch_half_staged(p, f, c, hupd, st);
     const int o = 1 - c;
     BA a = make_args(p);
     int dev = 0, cus = 256;
@@ -357,34 +368,134 @@ void launch_pair(const rbffd_plan* p, const rbffd_fields* f, int c, hipStream_t 
     const int64_t need = cdiv(a.N * a.KC, wpb);
     const int grid = (int)std::min<int64_t>(need, (int64_t)cus * p->var.persist);
     a.E = (const float*)f->E[c];
-    a.H = (const float*)f->H[c];
-    a.out = (float*)f->H[o];
-    a.a = (float)(p->dt / p->p.mu0);
-    hipLaunchKernelGGL(k_hb, dim3(grid), dim3(p->var.block), 0, st, a);
-    a.H = (const float*)f->H[o];
-    a.out = (float*)f->E[o];
-    a.a = (float)(p->dt / p->p.eps0);
-    hipLaunchKernelGGL(k_eb, dim3(grid), dim3(p->var.block), 0, st, a);
+    if (hupd) {
+        a.H = (const float*)f->H[c];
+        a.out = (float*)f->H[o];
+        a.a = (float)(p->dt / p->p.mu0);
+        hipLaunchKernelGGL(k_hb, dim3(grid), dim3(p->var.block), 0, st, a);
+    } else {
+        a.H = (const float*)f->H[o];
+        a.out = (float*)f->E[o];
+        a.a = (float)(p->dt / p->p.eps0);
+        hipLaunchKernelGGL(k_eb, dim3(grid), dim3(p->var.block), 0, st, a);
+    }
+}
+
+// ---- per-field energy (eq. 20) ---------------------------------------------
+// U_k = h^2 sum_i (E_ik^2 + eta0^2 |(H^n_ik + H^{n+1}_ik) / 2|^2) for every
+// field k, in FP64.  Pass 1: a wavefront reads one node's 64-field rows
+// (lane = field) and strides over nodes; a workgroup's four wavefronts are
+// summed in LDS into partial [block][K].  Pass 2 sums the partials of each
+// field in block order.  Both passes return at once unless the step counter
+// is a multiple of ``every``; the sample index is counter / every.
+__global__ __launch_bounds__(256) void k_benergy1(const float* E, const float* Ha, const float* Hb, int64_t N,
+                                                  int K, double wE, double wH, double* part, const int32_t* ctr,
+                                                  int every) {
+    if (*ctr % every) return;
+    __shared__ double sh[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int k = blockIdx.y * 64 + lane;
+    const int kk = k < K ? k : K - 1;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + wv; i < N; i += (int64_t)gridDim.x * 4) {
+        const double e = (double)E[i * K + kk];
+        const double hx = 0.5 * ((double)Ha[(i * 2) * K + kk] + (double)Hb[(i * 2) * K + kk]);
+        const double hy = 0.5 * ((double)Ha[(i * 2 + 1) * K + kk] + (double)Hb[(i * 2 + 1) * K + kk]);
+        acc += wE * e * e + wH * (hx * hx + hy * hy);
+    }
+    sh[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && k < K) part[(int64_t)blockIdx.x * K + k] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+}
+
+__global__ void k_benergy2(const double* part, int nb, int K, double* out, const int32_t* ctr, int every) {
+    const int n = *ctr;
+    if (n % every) return;
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= K) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * K + k];
+    out[(int64_t)(n / every) * K + k] = s;
+}
+
+__global__ void k_bctr_set(int32_t* ctr, int32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = v;
+}
+__global__ void k_bctr_inc(int32_t* ctr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += 1;
+}
+
+int energy_blocks(const rbffd_plan* p) {
+    const int64_t cap = (int64_t)RED_BLOCKS * 12 / p->K;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(cap, std::min<int64_t>(1024, cdiv(p->E.N, 64))));
+}
+
+void launch_benergy(const rbffd_plan* p, const rbffd_fields* f, int c, double* out, RunWS& w, int every,
+                    hipStream_t st) {
+    const int o = 1 - c;
+    const double wE = p->E.h * p->E.h;
+    const double wH = p->eta0 * p->eta0 * wE;
+    const int nb = energy_blocks(p);
+    const int kc = (int)cdiv(p->K, 64);
+    hipLaunchKernelGGL(k_benergy1, dim3(nb, kc), dim3(256), 0, st, (const float*)f->E[c], (const float*)f->H[c],
+                       (const float*)f->H[o], p->E.N, p->K, wE, wH, w.part, (const int32_t*)w.ctr, every);
+    hipLaunchKernelGGL(k_benergy2, dim3(kc), dim3(64), 0, st, (const double*)w.part, nb, p->K, out,
+                       (const int32_t*)w.ctr, every);
+}
+
+// one full step c -> o; with an energy request the sample of step n is taken
+// between the halves (E^n and both H levels are then available)
+void full_step_b(const rbffd_plan* p, const rbffd_fields* f, int c, double* energy_out, int every, RunWS* w,
+                 hipStream_t st) {
+    launch_half(p, f, c, true, st);
+    if (energy_out) launch_benergy(p, f, c, energy_out, *w, every, st);
+    launch_half(p, f, c, false, st);
+    if (energy_out) hipLaunchKernelGGL(k_bctr_inc, dim3(1), dim3(64), 0, st, w->ctr);
+}
+
+__global__ void k_field_gamma(float* gk, const double* c, int K, double fac, double gamma) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < K) gk[k] = (float)(c ? c[k] * fac : gamma);
+}
+
+// every field from one single-field state: dst[i][comp][k] = src[i][comp]
+__global__ void k_broadcast(const float* src, float* dst, int64_t rows, int K) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= rows * K) return;
+    dst[g] = src[g / K];
 }
 
 }  // namespace
+
+int fill_field_gamma(const rbffd_plan* p, const double* c_dev, hipStream_t st) {
+    if (!p->gk) return RBFFD_OK;
+    hipLaunchKernelGGL(k_field_gamma, dim3((unsigned)cdiv(p->K, 256)), dim3(256), 0, st, p->gk, c_dev, p->K,
+                       p->hv_fac, p->gamma);
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
 
 int batched_step(const rbffd_plan* p, rbffd_fields* f, int32_t nsteps, hipStream_t st) {
     if (f->eps_r) return set_err(p, RBFFD_ENOTSUP, "per-node eps_r is not supported for K-field batches");
     if (p->var.block > 256) return set_err(p, RBFFD_EINVAL, "K-field batches use at most 256 threads per workgroup");
     for (int s = 0; s < nsteps; ++s) {
-        launch_pair(p, f, f->cur, st);
+        full_step_b(p, f, f->cur, nullptr, 1, nullptr, st);
         f->cur = 1 - f->cur;
     }
     HIPCHK(p, hipGetLastError());
     return RBFFD_OK;
 }
 
-int batched_run(const rbffd_plan* p, rbffd_fields* f, const rbffd_run_args* a, void*, hipStream_t st) {
-    if (a->n_src || a->n_rcv || a->ckpt || (a->energy_out && a->energy_every))
-        return set_err(p, RBFFD_ENOTSUP, "K-field batches run without sources, receivers, energy or checkpoints");
+int batched_run(const rbffd_plan* p, rbffd_fields* f, const rbffd_run_args* a, void* ws, hipStream_t st) {
+    if (a->n_src || a->n_rcv || a->ckpt)
+        return set_err(p, RBFFD_ENOTSUP, "K-field batches run without sources, receivers or checkpoints");
     if (f->eps_r) return set_err(p, RBFFD_ENOTSUP, "per-node eps_r is not supported for K-field batches");
     if (p->var.block > 256) return set_err(p, RBFFD_EINVAL, "K-field batches use at most 256 threads per workgroup");
+    if (a->energy_out && a->energy_every < 0) return set_err(p, RBFFD_EINVAL, "energy_every < 0");
+    double* eo = (a->energy_out && a->energy_every > 0) ? a->energy_out : nullptr;
+    const int every = eo ? a->energy_every : 1;
+    RunWS w = run_ws(ws);
+    if (eo) hipLaunchKernelGGL(k_bctr_set, dim3(1), dim3(64), 0, st, w.ctr, 0);
     int s = 0;
     if (a->use_graph && a->T >= 4) {
         hipGraph_t g;
@@ -393,8 +504,8 @@ int batched_run(const rbffd_plan* p, rbffd_fields* f, const rbffd_run_args* a, v
         int rc = capture_stream(p, &cs);
         if (rc) return rc;
         HIPCHK(p, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        launch_pair(p, f, f->cur, cs);
-        launch_pair(p, f, 1 - f->cur, cs);
+        full_step_b(p, f, f->cur, eo, every, &w, cs);
+        full_step_b(p, f, 1 - f->cur, eo, every, &w, cs);
         HIPCHK(p, hipStreamEndCapture(cs, &g));
         HIPCHK(p, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
         for (; s + 2 <= a->T; s += 2) HIPCHK(p, hipGraphLaunch(ge, st));
@@ -402,9 +513,107 @@ int batched_run(const rbffd_plan* p, rbffd_fields* f, const rbffd_run_args* a, v
         HIPCHK(p, hipGraphDestroy(g));
     }
     for (; s < a->T; ++s) {
-        launch_pair(p, f, f->cur, st);
+        full_step_b(p, f, f->cur, eo, every, &w, st);
         f->cur = 1 - f->cur;
     }
     HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
+
+extern "C" int rbffd_set_field_hv(rbffd_plan* p, const double* c_dev, void* stream) {
+    if (!p) return RBFFD_EINVAL;
+    if (!p->ready) return set_err(p, RBFFD_ESTATE, "rbffd_weights has not run");
+    if (p->K < 2 || !p->gk) return set_err(p, RBFFD_ENOTSUP, "per-field hyperviscosity needs a K-field batch");
+    if (p->p.hv_alpha < 1) return set_err(p, RBFFD_ENOTSUP, "the plan has no hyperviscosity (hv_alpha = 0)");
+    return fill_field_gamma(p, c_dev, (hipStream_t)stream);
+}
+
+// K-section search of the lower edge of the accepted interval of c (Section
+// 5.1 parameter sweep, Section 6 energy band): every round runs the K fields
+// from the same state, field k with c_k = c_lo (c_hi / c_lo)^(k / (K - 1)),
+// and keeps the bracket [c_{k*-1}, c_{k*}] around the smallest accepted c.
+extern "C" int rbffd_hv_scan(rbffd_plan* p, rbffd_fields* f, rbffd_hv_scan_args* a, void* ws, void* stream) {
+    if (!p || !a) return RBFFD_EINVAL;
+    if (!p->ready) return set_err(p, RBFFD_ESTATE, "rbffd_weights has not run");
+    if (p->K < 3 || !p->gk) return set_err(p, RBFFD_ENOTSUP, "the scan needs a K-field batch with K >= 3");
+    if (p->p.hv_alpha < 1) return set_err(p, RBFFD_ENOTSUP, "the plan has no hyperviscosity (hv_alpha = 0)");
+    if (!f || !ws || !a->E0 || !a->H0 || !a->c_dev || !a->energy_dev)
+        return set_err(p, RBFFD_EINVAL, "scan needs fields, workspace, initial state and device buffers");
+    if (!(a->c_lo > 0 && a->c_hi > a->c_lo && std::isfinite(a->c_hi)))
+        return set_err(p, RBFFD_EINVAL, "need 0 < c_lo < c_hi");
+    if (a->rounds < 1 || a->T < 1 || a->energy_every < 1) return set_err(p, RBFFD_EINVAL, "rounds, T, energy_every >= 1");
+    if (!(a->u_lo < a->u_hi)) return set_err(p, RBFFD_EINVAL, "need u_lo < u_hi");
+    for (int b = 0; b < 2; ++b)
+        if (!f->E[b] || !f->H[b]) return set_err(p, RBFFD_EINVAL, "null field buffer");
+    if (f->cur != 0 && f->cur != 1) return set_err(p, RBFFD_EINVAL, "fields.cur must be 0 or 1");
+    hipStream_t st = (hipStream_t)stream;
+    const int K = p->K;
+    const int ne = (a->T - 1) / a->energy_every + 1;
+    std::vector<double> cs(K), en((size_t)ne * K);
+    double lo = a->c_lo, hi = a->c_hi, best = 0.0;
+    int status = 0, r = 0;
+    for (; r < a->rounds; ++r) {
+        for (int k = 0; k < K; ++k) cs[k] = lo * std::pow(hi / lo, (double)k / (double)(K - 1));
+        HIPCHK(p, hipMemcpyAsync(a->c_dev, cs.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
+        int rc = fill_field_gamma(p, a->c_dev, st);
+        if (rc) return rc;
+        const int64_t re = p->E.N * p->FE, rh = p->E.N * p->FH;
+        hipLaunchKernelGGL(k_broadcast, dim3((unsigned)cdiv(re * K, 256)), dim3(256), 0, st, (const float*)a->E0,
+                           (float*)f->E[f->cur], re, K);
+        hipLaunchKernelGGL(k_broadcast, dim3((unsigned)cdiv(rh * K, 256)), dim3(256), 0, st, (const float*)a->H0,
+                           (float*)f->H[f->cur], rh, K);
+        HIPCHK(p, hipGetLastError());
+        rbffd_run_args ra{};
+        ra.T = a->T;
+        ra.energy_every = a->energy_every;
+        ra.energy_out = a->energy_dev;
+        ra.use_graph = 1;
+        if ((rc = batched_run(p, f, &ra, ws, st))) return rc;
+        HIPCHK(p, hipMemcpyAsync(en.data(), a->energy_dev, en.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+        int first = -1;
+        for (int k = 0; k < K; ++k) {
+            double umin = INFINITY, umax = -INFINITY;
+            bool ok = true;
+            for (int s = 0; s < ne; ++s) {
+                const double u = en[(size_t)s * K + k] / en[k];
+                if (!std::isfinite(u)) {
+                    ok = false;
+                    umax = INFINITY;
+                    continue;
+                }
+                umin = std::min(umin, u);
+                umax = std::max(umax, u);
+                if (u < a->u_lo || u > a->u_hi) ok = false;
+            }
+            if (a->c_host) a->c_host[(size_t)r * K + k] = cs[k];
+            if (a->umin_host) a->umin_host[(size_t)r * K + k] = umin;
+            if (a->umax_host) a->umax_host[(size_t)r * K + k] = umax;
+            if (a->ok_host) a->ok_host[(size_t)r * K + k] = ok ? 1 : 0;
+            if (ok && first < 0) first = k;
+        }
+        if (first < 0) {
+            if (best == 0.0) status = 2;
+            ++r;
+            break;
+        }
+        best = cs[first];
+        if (first == 0) {
+            status = 1;
+            ++r;
+            break;
+        }
+        lo = cs[first - 1];
+        hi = cs[first];
+    }
+    a->rounds_done = r;
+    a->status = status;
+    a->c_best = best;
+    a->bracket[0] = lo;
+    a->bracket[1] = hi;
+    // later runs use the plan's c again
+    int rc = fill_field_gamma(p, nullptr, st);
+    if (rc) return rc;
+    HIPCHK(p, hipStreamSynchronize(st));
     return RBFFD_OK;
 }

@@ -96,6 +96,8 @@ struct rbffd_plan {
     int fe_comp = 1, fh_comp = 2;// physical components
     int K = 1;
     double dt = 0, gamma = 0, c0 = 1, eta0 = 1;
+    double hv_fac = 0;           // gamma / c = (-1)^(alpha-1) h^(2 alpha)
+    float* gk = nullptr;         // K-field batch: per-field gamma [K] (arena)
     NodeSet E, H;                // H unused unless two-set
     OpBlock opH, opE;            // operators of the H update and the E update
     bool collocated = true;
@@ -115,6 +117,26 @@ struct rbffd_plan {
     int ex_m[RBFFD_MAX_MONO][3];   // monomial exponents (curl)
     int ex_h[RBFFD_MAX_MONO][3];   // monomial exponents (hv)
 };
+
+// ---- run workspace: FP64 reduction partials, the device step counter -------
+constexpr int RED_BLOCKS = 1024;
+struct RunWS {
+    double* part;       // [RED_BLOCKS * 12]
+    int32_t* ctr;
+    double* misc;
+};
+inline RunWS run_ws(void* ws) {
+    RunWS w;
+    char* b = (char*)ws;
+    w.part = (double*)b;
+    w.ctr = (int32_t*)(b + RED_BLOCKS * 12 * 8);
+    w.misc = (double*)(b + RED_BLOCKS * 12 * 8 + 256);
+    return w;
+}
+
+// K-field batch: per-field gamma from per-field constants c (device [K]), or
+// every field the plan's gamma when c is null (batched.hip)
+int fill_field_gamma(const rbffd_plan* p, const double* c_dev, hipStream_t st);
 
 // ---- helpers --------------------------------------------------------------
 int set_err(const rbffd_plan* p, int code, const std::string& msg);

@@ -138,6 +138,7 @@ int64_t layout_arena(rbffd_plan* p, char* base, int64_t* ws, int64_t* adj_ws) {
         p->opE = p->opH;
         (void)keep;
     }
+    p->gk = p->K > 1 ? b.take<float>(p->K) : nullptr;
     if (ws) *ws = setup_ws_bytes(p);
     if (adj_ws) {
         const int64_t fb = field_elem_bytes(p->p.fdtype) > 4 ? 8 : 4;
@@ -214,7 +215,8 @@ extern "C" int rbffd_plan_create(const rbffd_params* prm, int64_t N, const doubl
     p->dt = q.dt > 0 ? q.dt : q.h / (10.0 * std::sqrt(2.0) * p->c0);
     if (q.hv_alpha > 0) {
         const double sgn = (q.hv_alpha - 1) % 2 == 0 ? 1.0 : -1.0;
-        p->gamma = q.hv_c * sgn * std::pow(q.h, 2 * q.hv_alpha);
+        p->hv_fac = sgn * std::pow(q.h, 2 * q.hv_alpha);
+        p->gamma = q.hv_c * p->hv_fac;
     }
     if (q.fdtype == RBFFD_F64 || q.fdtype == RBFFD_F32 || q.fdtype == RBFFD_BF16) {
         p->fe_comp = q.dim == 2 ? 1 : 3;

@@ -1245,6 +1245,7 @@ extern "C" int rbffd_weights(rbffd_plan* p, void* arena, void* ws, void* stream)
     if ((rc = pack_all(p, ws, st))) return rc;
     if (p->collocated && (rc = build_halos(p, ws, st))) return rc;
     if (p->p.adjoint && (rc = build_transpose(p, ws, st))) return rc;
+    if (p->K > 1 && (rc = fill_field_gamma(p, nullptr, st))) return rc;
     HIPCHK(p, hipStreamSynchronize(st));
     p->ready = true;
     return RBFFD_OK;

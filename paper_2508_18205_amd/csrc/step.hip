@@ -867,7 +867,6 @@ __global__ void k_ckpt(const uint16_t* E, int64_t e2, const uint16_t* H, int64_t
 }
 
 // ---- FP64 reductions --------------------------------------------------------
-constexpr int RED_BLOCKS = 1024;
 
 template <typename TS>
 __global__ __launch_bounds__(256) void k_energy1(const TS* E, int64_t NE, int FE, int fe, const TS* Ha, const TS* Hb,
@@ -969,21 +968,6 @@ __global__ void k_compare2(const double* part, int nb, int nc, double* out) {
 // Host side: launching one half step of either kind
 // ---------------------------------------------------------------------------
 namespace {
-
-struct RunWS {
-    double* part;       // [RED_BLOCKS * 12]
-    int32_t* ctr;
-    double* misc;
-};
-
-RunWS run_ws(void* ws) {
-    RunWS w;
-    char* b = (char*)ws;
-    w.part = (double*)b;
-    w.ctr = (int32_t*)(b + RED_BLOCKS * 12 * 8);
-    w.misc = (double*)(b + RED_BLOCKS * 12 * 8 + 256);
-    return w;
-}
 
 template <typename TS, typename TW>
 void fill_sa(const rbffd_plan* p, const OpBlock& o, SA<TS, TW>& a, bool hupd) {

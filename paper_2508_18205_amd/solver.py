@@ -237,7 +237,7 @@ class Solver:
         keep = []
         if energy_every:
             ne = (T - 1) // energy_every + 1
-            en = torch.zeros(ne, dtype=torch.float64, device=self.device)
+            en = torch.zeros((ne, self.K) if self.K > 1 else ne, dtype=torch.float64, device=self.device)
             a.energy_every, a.energy_out = energy_every, en.data_ptr()
             out["energy_t"] = en
         if src is not None:
@@ -269,6 +269,49 @@ class Solver:
         if energy_every:
             out["energy"] = out["energy_t"].cpu().numpy()
         return out
+
+    def set_field_hv(self, c=None):
+        """K-field batch: field k uses the hyperviscosity constant c[k] (None: the plan's c)."""
+        ct = None
+        if c is not None:
+            ct = torch.tensor(np.asarray(c, dtype=np.float64).reshape(self.K), device=self.device)
+        check(self.lib.rbffd_set_field_hv(self.plan, _ptr(ct) if ct is not None else None, self.stream()),
+              self.plan, "rbffd_set_field_hv")
+        self.sync()
+
+    def hv_scan(self, st, E0, H0, c_lo, c_hi, rounds, T, energy_every, band=(0.99, 1.01)):
+        """Search of the smallest accepted hyperviscosity constant (rbffd_hv_scan).
+
+        st: a K-field state whose buffers are overwritten; E0 [N, fe], H0 [N, fh]
+        one original-order initial state shared by every field.  Returns a dict
+        with status ("bracketed", "below", "none"), c_best, bracket and per-round
+        arrays c, ok, umin, umax [rounds_done, K].
+        """
+        K = self.K
+        E0t = self.to_internal(E0, self.FE)
+        H0t = self.to_internal(H0, self.FH)
+        ne = (int(T) - 1) // int(energy_every) + 1
+        cdev = torch.zeros(K, dtype=torch.float64, device=self.device)
+        edev = torch.zeros(ne * K, dtype=torch.float64, device=self.device)
+        ch = np.zeros((rounds, K))
+        umin = np.zeros((rounds, K))
+        umax = np.zeros((rounds, K))
+        ok = np.zeros((rounds, K), dtype=np.int32)
+        a = _abi.HvScanArgs()
+        a.E0, a.H0, a.c_lo, a.c_hi = _ptr(E0t), _ptr(H0t), float(c_lo), float(c_hi)
+        a.rounds, a.T, a.energy_every = int(rounds), int(T), int(energy_every)
+        a.u_lo, a.u_hi = float(band[0]), float(band[1])
+        a.c_dev, a.energy_dev = _ptr(cdev), _ptr(edev)
+        a.c_host, a.umin_host, a.umax_host, a.ok_host = (ch.ctypes.data, umin.ctypes.data, umax.ctypes.data,
+                                                         ok.ctypes.data)
+        f = st.struct()
+        check(self.lib.rbffd_hv_scan(self.plan, C.byref(f), C.byref(a), _ptr(self.ws), self.stream()), self.plan,
+              "rbffd_hv_scan")
+        st.cur = f.cur
+        r = a.rounds_done
+        return {"status": ("bracketed", "below", "none")[a.status], "c_best": a.c_best if a.c_best > 0 else None,
+                "bracket": (a.bracket[0], a.bracket[1]), "c": ch[:r], "ok": ok[:r].astype(bool),
+                "umin": umin[:r], "umax": umax[:r]}
 
     def adjoint(self, st_eps, T, ckpt, ckpt_every, grad_traces, src=None, rcv=None):
         """Gradients (grad_eps [N] original order, grad_amp [S]) of J(traces)."""

@@ -38,6 +38,10 @@ def test_struct_layouts_match_header_sizes():
     # params: 14 int32 + 7 doubles + 6 doubles
     assert C.sizeof(_abi.Params) == 14 * 4 + 13 * 8
     assert C.sizeof(_abi.Fields) == 5 * 8 + 8
+    # run args: 8 int32, 7 pointers, 1 double
+    assert C.sizeof(_abi.RunArgs) == 8 * 4 + 7 * 8 + 8
+    # scan args: 8 pointers, 7 doubles, 6 int32
+    assert C.sizeof(_abi.HvScanArgs) == 8 * 8 + 7 * 8 + 6 * 4
 
 
 def _params(_abi, **kw):
@@ -69,6 +73,9 @@ def test_plan_validation_and_sizes_on_host():
     assert s.arena_bytes > 0 and s.e_bytes == 121 * 8
     # out-of-order use is refused without touching the device
     assert lib.rbffd_get_perm(plan, 0, np.zeros(121, np.int32).ctypes.data, None) == _abi.ESTATE
+    sa = _abi.HvScanArgs()
+    assert lib.rbffd_hv_scan(plan, None, C.byref(sa), None, None) == _abi.ESTATE
+    assert lib.rbffd_set_field_hv(plan, None, None) == _abi.ESTATE
     lib.rbffd_plan_destroy(plan)
     # n must exceed M_m; stencils must fit; BF16 needs F32 weights
     for bad in (dict(n=6), dict(n=200), dict(fdtype=2, wdtype=0), dict(dim=4), dict(phs_k=4)):

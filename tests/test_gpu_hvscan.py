@@ -1,0 +1,141 @@
+"""Per-field hyperviscosity, per-field energy and the parameter search on the GPU.
+
+* Every field given the plan's c through rbffd_set_field_hv: bit-identical
+  to the plain K-field run.
+* K fields, each with its own c, from one state: fields and per-field energy
+  series (eq. 20) against the FP64 oracle run with that c (FP32 tolerance).
+* rbffd_hv_scan against the oracle's search on the same periodic strip: the
+  same candidates, energy ratios within FP32 tolerance (1e-4 for bounded
+  runs; for growing runs 1% of the growth, which amplifies the rounding), the
+  same decisions
+  wherever the oracle's ratios are not within 1e-3 of the band edges, hence
+  the same bracket.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2508_18205_amd import Solver  # noqa: E402
+from oracle import hvscan, knn, step as ostep, weights as OW  # noqa: E402
+from synth import configs, nodes, rng  # noqa: E402
+
+
+def _announce(msg):
+    print(msg, flush=True)
+
+
+def _strip(K):
+    nx, ny = 48, 6
+    Ly = ny / nx
+    xyz, flags, h = nodes.jittered_grid((nx, ny), hi=(1.0, Ly), periodic=True, seed=5)
+    N = xyz.shape[0]
+    noise = rng.uniform_range(5, 1, np.arange(N), -1.0, 1.0)
+    E0 = (np.sin(2 * math.pi * xyz[:, 0]) + 1e-3 * noise)[:, None]
+    H0 = np.zeros((N, 2))
+    dt = configs.SC * h
+    s = Solver(2, xyz, flags, h, 12, 2, 2, 1e-3 / dt, (0.0, 0.0), (1.0, Ly), n_hv=31, bc="PERIODIC",
+               precision="f32", K=K)
+    P = (1.0, Ly)
+    idx = knn.knn(xyz, 31, period=P)
+    op = {"curl_idx": idx[:, :12], "curl_w": OW.curl_weights(xyz, xyz, idx[:, :12], 2, period=P),
+          "hv_idx": idx, "hv_w": OW.hv_weights(xyz, xyz, idx, 2, period=P)}
+    return s, xyz, h, dt, E0, H0, op
+
+
+def _batch(s, E0, H0):
+    K = s.K
+    return s.state_batched(np.repeat(E0[None], K, 0), np.repeat(H0[None], K, 0))
+
+
+def test_uniform_field_hv_is_bit_identical():
+    _announce("per-field c = plan c: bit-identical")
+    s, xyz, h, dt, E0, H0, _ = _strip(16)
+    out = []
+    for mode in ("plan", "array", "reset"):
+        if mode == "array":
+            s.set_field_hv(np.full(16, 1e-3 / dt))
+        elif mode == "reset":
+            s.set_field_hv(np.full(16, 3e-4 / dt))
+            s.set_field_hv(None)
+        st = _batch(s, E0, H0)
+        s.run(st, 200, use_graph=True)
+        out.append((s.to_original(st.E), s.to_original(st.H)))
+    for o in out[1:]:
+        assert (o[0] == out[0][0]).all() and (o[1] == out[0][1]).all()
+
+
+def test_per_field_hv_and_energy_vs_oracle():
+    K = 8
+    _announce("per-field c and energy vs oracle")
+    s, xyz, h, dt, E0, H0, op = _strip(K)
+    chat = np.array([0.0, 1e-5, 1e-4, 3e-4, 1e-3, 2e-3, 3e-3, 1e-3])
+    s.set_field_hv(chat / dt)
+    T, every = 400, 20
+    st = _batch(s, E0, H0)
+    r = s.run(st, T, energy_every=every, use_graph=True)
+    en = r["energy"]                                   # [samples, K]
+    assert en.shape == ((T - 1) // every + 1, K)
+    Eb = s.to_original(st.E)[:, 0, :]                 # [N, K]
+    Hb = s.to_original(st.H)                           # [N, 2, K]
+    N = xyz.shape[0]
+    worst_f = worst_u = 0.0
+    for k in range(K):
+        g = ostep.hv_gamma(chat[k] / dt, 2, h)
+        Eo, Ho, eno, _ = ostep.run(E0, H0, op, op, dt, T, g, dt, np.ones((N, 1)), h_e=h, h_h=h,
+                                   energy_every=every)
+        ef = max(np.abs(Eb[:, k] - Eo[:, 0]).max() / np.abs(Eo).max(),
+                 np.abs(Hb[:, :, k] - Ho).max() / np.abs(Ho).max())
+        eu = np.abs(en[:, k] / en[0, k] - eno / eno[0]).max()
+        e0 = abs(en[0, k] / eno[0] - 1)
+        worst_f, worst_u = max(worst_f, ef), max(worst_u, eu, e0)
+    _announce(f"  fields {worst_f:.2e}, energy {worst_u:.2e}")
+    assert worst_f < 1e-5
+    assert worst_u < 1e-5
+    # the same c in two slots gives identical results
+    assert (Eb[:, 4] == Eb[:, 7]).all() and (en[:, 4] == en[:, 7]).all()
+
+
+def test_hv_scan_matches_oracle_search():
+    K, rounds, T, every = 8, 2, 1500, 50
+    band = (0.99, 1.01)
+    _announce(f"hv scan K={K} rounds={rounds} T={T}")
+    s, xyz, h, dt, E0, H0, op = _strip(K)
+    st = _batch(s, E0, H0)
+    g = s.hv_scan(st, E0, H0, 1e-5 / dt, 1e-2 / dt, rounds, T, every, band)
+    N = xyz.shape[0]
+    o = hvscan.hv_scan(E0, H0, op, op, dt, T, every, 2, h, dt, np.ones((N, 1)), 1e-5 / dt, 1e-2 / dt, K,
+                       rounds, band=band)
+    _announce(f"  gpu {g['status']} {g['bracket']}  oracle {o['status']} {o['bracket']}")
+    assert len(g["c"]) == len(o["history"])
+    for r, ((cs, ok), u) in enumerate(zip(o["history"], o["u"])):
+        assert np.allclose(g["c"][r], cs, rtol=1e-14, atol=0)
+        fin = np.isfinite(u).all(1)
+        umin = np.where(fin, u.min(1), np.nan)
+        umax = np.where(fin, u.max(1), np.inf)
+        for k in range(K):
+            if fin[k] and umax[k] < 1.05:
+                # bounded run: FP32 fields, FP64 energy sums
+                assert abs(g["umin"][r, k] - umin[k]) < 1e-4
+                assert abs(g["umax"][r, k] - umax[k]) < 1e-4
+            elif fin[k] and umax[k] < 1e3:
+                # a growing mode amplifies the FP32 rounding with its growth
+                assert abs(g["umax"][r, k] - umax[k]) < 1e-2 * (umax[k] - 1)
+            clear = (not fin[k]) or min(abs(umin[k] - band[0]), abs(umax[k] - band[1])) > 1e-3
+            if clear:
+                assert bool(g["ok"][r, k]) == bool(ok[k]), (r, k)
+    assert g["status"] == o["status"]
+    assert np.allclose(g["bracket"], o["bracket"], rtol=1e-14)
+    # the plan's c is back in effect after the scan
+    st = _batch(s, E0, H0)
+    s.run(st, 10)
+    s2, *_ = _strip(K)
+    st2 = _batch(s2, E0, H0)
+    s2.run(st2, 10)
+    assert (s.to_original(st.E) == s2.to_original(st2.E)).all()
