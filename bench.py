@@ -13,6 +13,7 @@ roofline of the dominant kernel (the H update) and the FP64 CPU oracle timed on
 a bounded sample of the same workload.
 """
 import argparse
+import ctypes
 import json
 import math
 import os
@@ -122,8 +123,6 @@ def main():
     ap.add_argument("--legs", default="fp64,accuracy,batched,accuracy_alpha2,bf16,adjoint,stag2,hv_scan,3d",
                     help="comma-separated extra legs to run after the headline measurement")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="also run a plain device copy of this size (for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this "
@@ -174,14 +173,6 @@ def main():
         variant = s.autotune(st, reps=10)
         st = s.state(w.E0, w.H0)
         log(f"tuned variant: {variant}")
-    if args.copy_probe_mib:
-        a = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
-
     s.run(st, args.warmup, use_graph=True)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -215,7 +206,7 @@ def main():
         traffic = counted_traffic(kname)
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-probe scaled)",
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by the same counter read for the 2 GiB stream copy)",
             "kernel": f"{kname}<float,float> ({'H' if dominant == 'H' else 'E'} update)",
             "alg_bytes_per_launch": int(bh if dominant == "H" else be),
             "avg_launch_us": round((th if dominant == "H" else te) * 1e6, 2),
@@ -227,21 +218,28 @@ def main():
         cgbs = traffic / (th if dominant == "H" else te) / 1e9
         roof["counted_GBs"] = round(cgbs, 1)
         roof["counted_frac"] = round(cgbs / HBM_PEAK_GBS, 4)
-    # measured device-copy ceiling (read + write bytes of a 2 GiB copy)
+    # measured streaming ceiling: the library's 16-byte copy kernel over 2 GiB
+    # (read + write bytes / time)
+    from paper_2508_18205_amd import _abi as _ab
+    lib = _ab.load()
     ca = torch.empty(1 << 29, dtype=torch.float32, device=dev)
     cb = torch.empty_like(ca)
     ca.fill_(1.0)
+    nb_ = ca.numel() * 4
+    sp = ctypes.c_void_p(stream.cuda_stream)
     for _ in range(3):
-        cb.copy_(ca)
+        _ab.check(lib.rbffd_stream_copy(ctypes.c_void_p(ca.data_ptr()), ctypes.c_void_p(cb.data_ptr()), nb_, sp))
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(10):
-        cb.copy_(ca)
+        lib.rbffd_stream_copy(ctypes.c_void_p(ca.data_ptr()), ctypes.c_void_p(cb.data_ptr()), nb_, sp)
     e1.record(stream)
     torch.cuda.synchronize()
-    copy_gbs = 2 * ca.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    copy_gbs = 2 * nb_ * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    assert bool((cb == 1.0).all())
     roof["copy_ceiling_GBs"] = round(copy_gbs, 1)
-    roof["frac_of_copy_ceiling"] = round(ach / copy_gbs, 4)
+    if "counted_GBs" in roof:
+        roof["counted_frac_of_copy_ceiling"] = round(roof["counted_GBs"] / copy_gbs, 4)
     del ca, cb
     torch.cuda.empty_cache()
     log(f"device copy ceiling: {copy_gbs:.0f} GB/s")
@@ -453,25 +451,36 @@ def main():
         # hyperviscosity parameter search on the 1M-node set: K = 64 values of
         # c per round advanced together (per-field gamma, per-field energy)
         scans = {}
-        for alpha, nhv, lo, hi, rounds in ((w.alpha, w.n_hv, 1e-8, 1e-1, 2), (2, 31, 1e-7, 1e-1, 2)):
-            ws_ = configs.Workload(w.name, w.dim, w.xyz, w.flags, w.h, w.n, w.m, alpha, nhv, 1e-3, 2000)
+        Ts = w.steps
+        # the node-sum energy of the PEC cavity swings by about 1% as the pulse
+        # meets the walls, so the alpha = 2 search also runs with a 2% band
+        for alpha, nhv, lo, hi, rounds, band in ((w.alpha, w.n_hv, 1e-8, 1e-1, 1, (0.99, 1.01)),
+                                                 (2, 31, 1e-7, 1e-1, 1, (0.99, 1.01)),
+                                                 (2, 31, 1e-7, 1e-1, 2, (0.98, 1.02))):
+            ws_ = configs.Workload(w.name, w.dim, w.xyz, w.flags, w.h, w.n, w.m, alpha, nhv, 1e-3, Ts)
             sk = Solver.from_workload(ws_, precision="f32", K=64)
-            stk = sk.state_batched(np.repeat(w.E0[None], 64, 0), np.repeat(w.H0[None], 64, 0))
+            # the scan fills the buffers from (E0, H0) itself
+            from paper_2508_18205_amd.solver import State
+            zE = torch.zeros((w.N, 1, 64), dtype=torch.float32, device=dev)
+            zH = torch.zeros((w.N, 2, 64), dtype=torch.float32, device=dev)
+            stk = State([zE, torch.zeros_like(zE)], [zH, torch.zeros_like(zH)], 0, None)
             torch.cuda.synchronize()
             t0 = time.time()
-            r = sk.hv_scan(stk, w.E0, w.H0, lo / w.dt, hi / w.dt, rounds, 2000, 100)
+            r = sk.hv_scan(stk, w.E0, w.H0, lo / w.dt, hi / w.dt, rounds, Ts, 100, band)
             tsc = time.time() - t0
             acc = [float(c * w.dt) for c, o in zip(r["c"].ravel(), r["ok"].ravel()) if o]
-            scans[f"alpha{alpha}"] = {
-                "n_hv": nhv, "chat_range": [lo, hi], "K": 64, "rounds_done": int(len(r["c"])), "steps": 2000,
-                "band": [0.99, 1.01], "status": r["status"],
+            scans[f"alpha{alpha}_band{round((band[1] - 1) * 100)}pct"] = {
+                "n_hv": nhv, "chat_range": [lo, hi], "K": 64, "rounds_done": int(len(r["c"])), "steps": Ts,
+                "band": list(band), "status": r["status"],
                 "chat_best": (r["c_best"] * w.dt) if r["c_best"] else None,
                 "chat_bracket": [r["bracket"][0] * w.dt, r["bracket"][1] * w.dt],
                 "accepted_chat_round1": [float(c * w.dt) for c, o in zip(r["c"][0], r["ok"][0]) if o],
                 "accepted_total": len(acc),
                 "umax_min_round1": float(np.min(r["umax"][0])),
+                "chat_at_umax_min_round1": float(r["c"][0][int(np.argmin(r["umax"][0]))] * w.dt),
+                "umin_there": float(r["umin"][0][int(np.argmin(r["umax"][0]))]),
                 "scan_s": round(tsc, 2),
-                "field_node_steps_per_s": w.N * 64 * 2000 * len(r["c"]) / tsc}
+                "field_node_steps_per_s": w.N * 64 * Ts * len(r["c"]) / tsc}
             del sk, stk
             torch.cuda.empty_cache()
         extras["hv_scan"] = scans

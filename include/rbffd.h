@@ -317,6 +317,13 @@ int rbffd_autotune(rbffd_plan* plan, rbffd_fields* f, int32_t reps, void* stream
 int rbffd_get_variant(const rbffd_plan* plan, int32_t* out_variant);
 int rbffd_set_variant(rbffd_plan* plan, int32_t block, int32_t xcd, int32_t lds, int32_t persist);
 
+/* ---- measurement ------------------------------------------------------------
+ * rbffd_stream_copy: dst[0 .. bytes) = src[0 .. bytes) on the stream with 16-byte
+ * non-temporal accesses (device pointers, 16-byte aligned, bytes a multiple of
+ * 16; the ranges must not overlap).  Timing it gives the practical HBM
+ * ceiling (2 * bytes moved) that the step kernels are compared with. */
+int rbffd_stream_copy(const void* src, void* dst, int64_t bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

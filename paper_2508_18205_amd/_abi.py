@@ -97,6 +97,7 @@ PROTOTYPES = {
     "rbffd_set_variant": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "rbffd_set_field_hv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "rbffd_hv_scan": (C.c_int, [C.c_void_p, C.POINTER(Fields), C.POINTER(HvScanArgs), C.c_void_p, C.c_void_p]),
+    "rbffd_stream_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
 }
 
 _lib = None
