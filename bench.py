@@ -492,6 +492,9 @@ def main():
         for prec in ("f32", "f64"):
             s3, t3 = setup_w(w3, prec)
             a3 = s3.state(w3.E0, w3.H0)
+            if not args.no_tune:
+                s3.autotune(a3, reps=3)
+                a3 = s3.state(w3.E0, w3.H0)
             s3.run(a3, 10, use_graph=True)
             torch.cuda.synchronize()
             e0.record(stream)
@@ -502,11 +505,13 @@ def main():
             th3, te3 = time_halves(s3, a3, 10, torch)
             a3 = s3.state(w3.E0, w3.H0)
             s3.run(a3, w3.steps, use_graph=True)
-            r3[prec] = dict(rate=rate, setup=t3, th=th3, te=te3, E=s3.E_original(a3), H=s3.H_original(a3))
+            r3[prec] = dict(rate=rate, setup=t3, th=th3, te=te3, E=s3.E_original(a3), H=s3.H_original(a3),
+                            variant=s3.variant())
             del s3, a3
             torch.cuda.empty_cache()
         sw3 = 4
         bh3 = alg_bytes_half(w3.n, w3.n_hv, 3, sw3, 4, 3, 3, 0) * w3.N
+        bh3d = alg_bytes_half(w3.n, w3.n_hv, 3, 8, 8, 3, 3, 0) * w3.N
         extras["tm111_3d"] = {
             "N": w3.N, "n": w3.n, "n_hv": w3.n_hv, "value_f32": r3["f32"]["rate"], "value_f64": r3["f64"]["rate"],
             "unit": "node-steps/s", "fp32_over_fp64": round(r3["f32"]["rate"] / r3["f64"]["rate"], 3),
@@ -514,6 +519,10 @@ def main():
             "h_update_us": round(r3["f32"]["th"] * 1e6, 1), "e_update_us": round(r3["f32"]["te"] * 1e6, 1),
             "h_update_GBs": round(bh3 / r3["f32"]["th"] / 1e9, 1),
             "h_update_frac": round(bh3 / r3["f32"]["th"] / 1e9 / HBM_PEAK_GBS, 4),
+            "variant_f32": r3["f32"]["variant"], "variant_f64": r3["f64"]["variant"],
+            "h_update_us_f64": round(r3["f64"]["th"] * 1e6, 1), "e_update_us_f64": round(r3["f64"]["te"] * 1e6, 1),
+            "h_update_GBs_f64": round(bh3d / r3["f64"]["th"] / 1e9, 1),
+            "h_update_frac_f64": round(bh3d / r3["f64"]["th"] / 1e9 / HBM_PEAK_GBS, 4),
             "steps_accuracy": w3.steps,
             "fp32_vs_fp64_rel_l2_E": rl2(r3["f32"]["E"], r3["f64"]["E"]),
             "fp32_vs_fp64_rel_l2_H": rl2(r3["f32"]["H"], r3["f64"]["H"])}

@@ -58,6 +58,8 @@ struct OpBlock {
     int32_t Q8 = 0;
     int64_t nwg = 0;
     int32_t hmax = 0;              // longest halo list (0 = staging unavailable)
+    int32_t stage = 0;             // single field: 1 = both operands staged together,
+                                   // 2 = one operand at a time (3D), 0 = none
     // transposed operator for the adjoint (collocated 2D)
     int64_t* t_off = nullptr;      // [tiles + 1] start of each tile's entries
     int32_t* t_width = nullptr;    // [tiles]

@@ -1205,11 +1205,23 @@ int build_halos(rbffd_plan* p, void* wsp, hipStream_t st) {
     int32_t mx = 0;
     for (int64_t t = 0; t < o.nwg; ++t) mx = std::max(mx, off[t + 1] - off[t]);
     // staging only when a workgroup's list fits the LDS budget and 16-bit positions
-    const int fb = field_elem_bytes(p->p.fdtype) == 8 ? 8 : 4;
-    // single field: one value per component; batch: a 16-field slice per component
-    const int64_t per = batch ? (int64_t)(p->fe_comp + p->fh_comp) * 8 * 4 : (int64_t)(p->FE + p->FH) * fb;
-    const int64_t budget = batch ? RBFFD_LDS_BUDGET_BATCH : RBFFD_LDS_BUDGET;
-    o.hmax = (mx < 65536 && (int64_t)mx * per <= budget) ? mx : 0;
+    o.stage = 0;
+    o.hmax = 0;
+    if (mx < 65536) {
+        const int64_t fb = field_elem_bytes(p->p.fdtype) == 8 ? 8 : 4;
+        if (batch) {
+            // an 8-field slice per component
+            if ((int64_t)mx * (p->fe_comp + p->fh_comp) * 8 * 4 <= RBFFD_LDS_BUDGET_BATCH) o.hmax = mx;
+        } else if (p->dim == 2) {
+            // E values (rounded up to 4 entries) and (Hx, Hy) pairs, as the 2D kernels lay them out
+            if ((((int64_t)mx + 3) / 4 * 4 + 2 * (int64_t)mx) * fb <= RBFFD_LDS_BUDGET) o.stage = 1;
+        } else {
+            // packed 3-vectors: both fields together, else one at a time
+            if (6 * (int64_t)mx * fb <= RBFFD_LDS_BUDGET) o.stage = 1;
+            else if (3 * (int64_t)mx * fb <= RBFFD_LDS_BUDGET) o.stage = 2;
+        }
+        if (o.stage) o.hmax = mx;
+    }
     p->opE = p->opH;
     return RBFFD_OK;
 }

@@ -816,6 +816,154 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
     }
 }
 
+// ---- 3D, two-phase staging ----------------------------------------------------
+// When the halo values of both operands do not fit the LDS budget together
+// (FP64), the operand of the curl is staged and summed first, then the same
+// LDS holds the operand of the hyperviscosity term.  Every accumulator runs
+// over the slots in the same order as in the kernels above, so the results
+// are the same.  Workgroups keep their idle wavefronts (a partial last
+// workgroup) through both barriers.
+template <typename TS>
+__device__ __forceinline__ void stage_vec3(const TS* F, const int32_t* list, int hc,
+                                           typename Store<TS>::C* s) {
+    using S = Store<TS>;
+    for (int k = threadIdx.x; k < hc; k += blockDim.x) {
+        typename S::C v[3];
+        S::ld3(F, list[k], v[0], v[1], v[2]);
+        st_lds3(s + 3 * k, v);
+    }
+}
+
+// curl sums over the curl slots: d_x, d_y, d_z of the staged 3-vector field
+// (reference values f0) into the six accumulators c[0..5] =
+// (x f_y, x f_z, y f_x, y f_z, z f_x, z f_y)
+template <typename TC, typename TW>
+__device__ __forceinline__ void curl_sums3(const TC* sF, const uint4* pl, const TW* pc, int C4, const TC (&f0)[3],
+                                           TC (&c)[6]) {
+    uint4 li = ldu4s(pl);
+    TW nx[4] = {0, 0, 0, 0}, ny[4] = {0, 0, 0, 0}, nz[4] = {0, 0, 0, 0}, nh[4];
+    load3(pc, (const TW*)nullptr, 0, C4, 0, nx, ny, nz, nh);
+    for (int q = 0; q < C4; ++q) {
+        const uint4 lc = li;
+        TW wx[4], wy[4], wz[4];
+        copy4(wx, nx); copy4(wy, ny); copy4(wz, nz);
+        if (q + 1 < C4) {
+            if (((q + 1) & 1) == 0) li = ldu4s(pl + ((q + 1) >> 1) * RBFFD_TILE);
+            load3(pc, (const TW*)nullptr, q + 1, C4, 0, nx, ny, nz, nh);
+        }
+        const int hf = q & 1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC v[3];
+            ld_lds3(sF + 3 * pos4(lc, hf, u), v);
+            const TC fx = v[0] - f0[0], fy = v[1] - f0[1], fz = v[2] - f0[2];
+            c[0] += (TC)wx[u] * fy; c[1] += (TC)wx[u] * fz;
+            c[2] += (TC)wy[u] * fx; c[3] += (TC)wy[u] * fz;
+            c[4] += (TC)wz[u] * fx; c[5] += (TC)wz[u] * fy;
+        }
+    }
+}
+
+// hyperviscosity sums over the HV slots of the staged 3-vector field
+template <typename TC, typename TW>
+__device__ __forceinline__ void hv_sums3(const TC* sF, const uint4* pl, const TW* ph, int V4, const TC (&f0)[3],
+                                         TC (&v3)[3]) {
+    uint4 li = ldu4s(pl);
+    TW nx[4], ny[4], nz[4], nh[4] = {0, 0, 0, 0};
+    load3((const TW*)nullptr, ph, 0, 0, V4, nx, ny, nz, nh);
+    for (int q = 0; q < V4; ++q) {
+        const uint4 lc = li;
+        TW wh[4];
+        copy4(wh, nh);
+        if (q + 1 < V4) {
+            if (((q + 1) & 1) == 0) li = ldu4s(pl + ((q + 1) >> 1) * RBFFD_TILE);
+            load3((const TW*)nullptr, ph, q + 1, 0, V4, nx, ny, nz, nh);
+        }
+        const int hf = q & 1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC v[3];
+            ld_lds3(sF + 3 * pos4(lc, hf, u), v);
+            v3[0] += (TC)wh[u] * (v[0] - f0[0]);
+            v3[1] += (TC)wh[u] * (v[1] - f0[1]);
+            v3[2] += (TC)wh[u] * (v[2] - f0[2]);
+        }
+    }
+}
+
+template <typename TS, typename TW>
+__global__ __launch_bounds__(256) void k_h3p(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    TC* sF = lds_base<TC>();
+    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
+    const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
+    const bool live = tile < a.tiles;
+    const int64_t tl = live ? tile : a.tiles - 1;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tl * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    TC e0[3], h0v[3];
+    S::ld3(a.E, ic, e0[0], e0[1], e0[2]);
+    S::ld3(a.H, ic, h0v[0], h0v[1], h0v[2]);
+    TC c[6] = {0, 0, 0, 0, 0, 0}, v[3] = {0, 0, 0};
+    const uint4* pl = a.lidx + tl * a.Q8 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tl * a.C4 * 3 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tl * a.V4 * RBFFD_TILE + lane) * 4;
+    stage_vec3<TS>(a.E, a.hpool + h0, hc, sF);
+    __syncthreads();
+    if (live) curl_sums3<TC, TW>(sF, pl, pc, a.C4, e0, c);
+    __syncthreads();
+    stage_vec3<TS>(a.H, a.hpool + h0, hc, sF);
+    __syncthreads();
+    if (live) hv_sums3<TC, TW>(sF, pl, ph, a.V4, h0v, v);
+    if (live && i < a.N) {
+        const TC A = (TC)a.a, G = (TC)a.g;
+        // c = (xEy, xEz, yEx, yEz, zEx, zEy)
+        S::st3(a.out, i, h0v[0] - A * ((c[3] - c[5]) - G * v[0]), h0v[1] - A * ((c[4] - c[1]) - G * v[1]),
+               h0v[2] - A * ((c[0] - c[2]) - G * v[2]));
+    }
+}
+
+template <typename TS, typename TW>
+__global__ __launch_bounds__(256) void k_e3p(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    TC* sF = lds_base<TC>();
+    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
+    const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
+    const bool live = tile < a.tiles;
+    const int64_t tl = live ? tile : a.tiles - 1;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = tl * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    TC e0[3], h0v[3];
+    S::ld3(a.E, ic, e0[0], e0[1], e0[2]);
+    S::ld3(a.H, ic, h0v[0], h0v[1], h0v[2]);
+    TC c[6] = {0, 0, 0, 0, 0, 0}, v[3] = {0, 0, 0};
+    const uint4* pl = a.lidx + tl * a.Q8 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + (tl * a.C4 * 3 * RBFFD_TILE + lane) * 4;
+    const TW* ph = a.wh + (tl * a.V4 * RBFFD_TILE + lane) * 4;
+    stage_vec3<TS>(a.H, a.hpool + h0, hc, sF);
+    __syncthreads();
+    if (live) curl_sums3<TC, TW>(sF, pl, pc, a.C4, h0v, c);
+    __syncthreads();
+    stage_vec3<TS>(a.E, a.hpool + h0, hc, sF);
+    __syncthreads();
+    if (live) hv_sums3<TC, TW>(sF, pl, ph, a.V4, e0, v);
+    if (live && i < a.N) {
+        const TC k = kappa_of(a, i), G = (TC)a.g;
+        const uint8_t m = a.emask[i];
+        // c = (xHy, xHz, yHx, yHz, zHx, zHy)
+        const TC nx = (m & 1) ? e0[0] + k * ((c[3] - c[5]) + G * v[0]) : (TC)0;
+        const TC ny = (m & 2) ? e0[1] + k * ((c[4] - c[1]) + G * v[1]) : (TC)0;
+        const TC nz = (m & 4) ? e0[2] + k * ((c[0] - c[2]) + G * v[2]) : (TC)0;
+        S::st3(a.out, i, nx, ny, nz);
+    }
+}
+
 // ---- per-step auxiliaries (read the device step counter) --------------------
 // src: E[node] += amp * wave[n * S + s] after the bracket (PEC nodes stay 0)
 template <typename TS>
@@ -1011,10 +1159,14 @@ void launch_half(const rbffd_plan* p, bool hupd, const void* E, const void* H, v
             const size_t lds = (size_t)(((o.hmax + 3) & ~3) + 2 * o.hmax) * sizeof(TC);
             if (hupd) hipLaunchKernelGGL((k_h2l<TS, TW>), grid, block, lds, st, a);
             else hipLaunchKernelGGL((k_e2l<TS, TW>), grid, block, lds, st, a);
-        } else {
+        } else if (o.stage == 1 && p->var.lds != 2) {
             const size_t lds = (size_t)6 * o.hmax * sizeof(TC);
             if (hupd) hipLaunchKernelGGL((k_h3l<TS, TW>), grid, block, lds, st, a);
             else hipLaunchKernelGGL((k_e3l<TS, TW>), grid, block, lds, st, a);
+        } else {
+            const size_t lds = (size_t)3 * o.hmax * sizeof(TC);
+            if (hupd) hipLaunchKernelGGL((k_h3p<TS, TW>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_e3p<TS, TW>), grid, block, lds, st, a);
         }
         return;
     }
@@ -1292,6 +1444,8 @@ extern "C" int rbffd_autotune(rbffd_plan* p, rbffd_fields* f, int32_t reps, void
             for (int pe : {8, 16}) cand.push_back(Variant{256, 1, pe, 1});
         } else {
             for (int x : {0, 1}) cand.push_back(Variant{256, x, 8, 1});
+            // 3D with both operands fitting: also the one-operand-at-a-time kernels
+            if (p->dim == 3 && p->opH.stage == 1) cand.push_back(Variant{256, 1, 8, 2});
         }
     }
     Variant best = p->var;

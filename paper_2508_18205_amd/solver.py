@@ -371,5 +371,5 @@ class Solver:
     def variant(self):
         v = C.c_int32()
         self.lib.rbffd_get_variant(self.plan, C.byref(v))
-        return {"block": v.value & 0xFFFF, "xcd": (v.value >> 16) & 1, "lds": (v.value >> 17) & 1,
+        return {"block": v.value & 0xFFFF, "xcd": (v.value >> 16) & 1, "lds": (v.value >> 17) & 7,
                 "persist": (v.value >> 20) & 0xFF}

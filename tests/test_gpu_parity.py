@@ -250,10 +250,11 @@ def test_batched_equals_single_runs(lds):
     assert worst < 1e-6
 
 
-@pytest.mark.parametrize("case", ["2d_f32", "2d_f64", "3d_f32"])
+@pytest.mark.parametrize("case", ["2d_f32", "2d_f64", "3d_f32", "3d_f64"])
 def test_staged_and_global_kernels_agree(case):
     # LDS-staged (halo list + 16-bit positions) vs global-gather kernels: same
-    # arithmetic in the same order, so the results must be identical
+    # arithmetic in the same order, so the results must be identical; in 3D
+    # also the kernels that stage one operand at a time (lds = 2)
     _announce(f"staged vs global kernels {case}")
     if case.startswith("2d"):
         w = configs.pulse_2d(r=0.02, chat=1e-3, alpha=2, steps=200)
@@ -262,13 +263,14 @@ def test_staged_and_global_kernels_agree(case):
     prec = case[-3:]
     s = Solver.from_workload(w, precision=prec)
     out = []
-    for lds in (1, 0):
+    for lds in ((1, 0, 2) if case.startswith("3d") else (1, 0)):
         s.set_variant(block=256, xcd=1, lds=lds)
         st = s.state(w.E0, w.H0)
         s.step(st, w.steps)
         out.append((s.E_original(st), s.H_original(st)))
     assert s.sizes.N == w.N
-    assert (out[0][0] == out[1][0]).all() and (out[0][1] == out[1][1]).all()
+    for o in out[1:]:
+        assert (out[0][0] == o[0]).all() and (out[0][1] == o[1]).all()
 
 
 def test_rcm_order_bit_exact():
