@@ -162,17 +162,40 @@ __device__ __forceinline__ int posq(const uint4& v, int half, int u) {
     return (int)((u & 1) ? (w >> 16) : (w & 0xFFFFu));
 }
 
+// The slice of every halo row (E, Hx, Hy) into LDS.  Each round a thread
+// takes SB pieces: all their list values are loaded, then all their 16-byte
+// field pieces, then the LDS stores, so that the loads are in flight together.
 template <int KSL>
 __device__ __forceinline__ void stage_slice(const BLA& a, float* sm, int64_t tile, int ks) {
+    constexpr int SB = 8;
     const int h0 = a.hoff[tile], hc = a.hoff[tile + 1] - h0;
     const int64_t K = a.K;
     const int kof = ks * KSL;
     constexpr int Q = KSL / 4;            // 16-byte pieces per row slice
-    for (int it = threadIdx.x; it < hc * 3 * Q; it += blockDim.x) {
-        const int k = it / (3 * Q), r = it - k * (3 * Q), c = r / Q, q = r - c * Q;
-        const int64_t j = a.hpool[h0 + k];
-        const float* src = c == 0 ? a.E + j * K : a.H + (j * 2 + (c - 1)) * K;
-        stf4(sm + (k * 3 + c) * KSL + q * 4, ldf4(src + kof + q * 4));
+    const int items = hc * 3 * Q, nt = (int)blockDim.x, t = (int)threadIdx.x;
+    for (int base = 0; base < items; base += SB * nt) {
+        int j[SB];
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+            const int it = base + b * nt + t;
+            j[b] = it < items ? a.hpool[h0 + it / (3 * Q)] : -1;
+        }
+        f4 v[SB];
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+            if (j[b] < 0) continue;
+            const int it = base + b * nt + t;
+            const int r = it % (3 * Q), c = r / Q, q = r - c * Q;
+            const float* src = c == 0 ? a.E + (int64_t)j[b] * K : a.H + ((int64_t)j[b] * 2 + (c - 1)) * K;
+            v[b] = ldf4(src + kof + q * 4);
+        }
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+            if (j[b] < 0) continue;
+            const int it = base + b * nt + t;
+            const int k = it / (3 * Q), r = it - k * (3 * Q), c = r / Q, q = r - c * Q;
+            stf4(sm + (k * 3 + c) * KSL + q * 4, v[b]);
+        }
     }
 }
 

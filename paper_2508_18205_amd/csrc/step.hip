@@ -541,6 +541,39 @@ __device__ __forceinline__ TC* lds_base() {
     return reinterpret_cast<TC*>(smem_raw);
 }
 
+// Halo staging with several loads in flight per thread: each round takes up
+// to SB list entries per thread, loads all their list values, then all their
+// field values, then stores them (a plain loop waits for each load in turn).
+// ld(j) returns the staged value of source node j, st(k, v) stores entry k.
+template <int SB, typename V, typename LD, typename ST>
+__device__ __forceinline__ void stage_rounds(const int32_t* list, int hc, LD ld, ST st) {
+    const int nt = (int)blockDim.x, t = (int)threadIdx.x;
+    for (int base = 0; base < hc; base += SB * nt) {
+        int j[SB];
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+            const int k = base + b * nt + t;
+            j[b] = k < hc ? list[k] : -1;
+        }
+        V v[SB];
+#pragma unroll
+        for (int b = 0; b < SB; ++b)
+            if (j[b] >= 0) v[b] = ld(j[b]);
+#pragma unroll
+        for (int b = 0; b < SB; ++b)
+            if (j[b] >= 0) st(base + b * nt + t, v[b]);
+    }
+}
+
+template <typename TC>
+struct Val3 {
+    TC x, y, z;
+};
+template <typename TC>
+struct Val6 {
+    TC v[6];
+};
+
 template <typename TS, typename TW>
 __global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
     using S = Store<TS>;
@@ -549,13 +582,18 @@ __global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
     TC* sH = sE + ((a.hmax + 3) & ~3);                 // pairs (Hx, Hy)
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
-    for (int k = threadIdx.x; k < hc; k += blockDim.x) {
-        const int j = a.hpool[h0 + k];
-        sE[k] = S::ld1(a.E, j);
-        TC hx, hy;
-        S::ld2(a.H, j, hx, hy);
-        st_lds2(sH + 2 * k, hx, hy);
-    }
+    stage_rounds<4, Val3<TC>>(
+        a.hpool + h0, hc,
+        [&](int j) {
+            Val3<TC> v;
+            v.x = S::ld1(a.E, j);
+            S::ld2(a.H, j, v.y, v.z);
+            return v;
+        },
+        [&](int k, const Val3<TC>& v) {
+            sE[k] = v.x;
+            st_lds2(sH + 2 * k, v.y, v.z);
+        });
     __syncthreads();
     const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
     if (tile >= a.tiles) return;
@@ -615,13 +653,18 @@ __global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
     TC* sH = sE + ((a.hmax + 3) & ~3);
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
-    for (int k = threadIdx.x; k < hc; k += blockDim.x) {
-        const int j = a.hpool[h0 + k];
-        sE[k] = S::ld1(a.E, j);
-        TC hx, hy;
-        S::ld2(a.H, j, hx, hy);
-        st_lds2(sH + 2 * k, hx, hy);
-    }
+    stage_rounds<4, Val3<TC>>(
+        a.hpool + h0, hc,
+        [&](int j) {
+            Val3<TC> v;
+            v.x = S::ld1(a.E, j);
+            S::ld2(a.H, j, v.y, v.z);
+            return v;
+        },
+        [&](int k, const Val3<TC>& v) {
+            sE[k] = v.x;
+            st_lds2(sH + 2 * k, v.y, v.z);
+        });
     __syncthreads();
     const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
     if (tile >= a.tiles) return;
@@ -676,14 +719,19 @@ __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
     TC* sH = sE + 3 * (int64_t)a.hmax;
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
-    for (int k = threadIdx.x; k < hc; k += blockDim.x) {
-        const int j = a.hpool[h0 + k];
-        TC e[3], hh[3];
-        S::ld3(a.E, j, e[0], e[1], e[2]);
-        S::ld3(a.H, j, hh[0], hh[1], hh[2]);
-        st_lds3(sE + 3 * k, e);
-        st_lds3(sH + 3 * k, hh);
-    }
+    stage_rounds<4, Val6<TC>>(
+        a.hpool + h0, hc,
+        [&](int j) {
+            Val6<TC> v;
+            S::ld3(a.E, j, v.v[0], v.v[1], v.v[2]);
+            S::ld3(a.H, j, v.v[3], v.v[4], v.v[5]);
+            return v;
+        },
+        [&](int k, const Val6<TC>& v) {
+            const TC e[3] = {v.v[0], v.v[1], v.v[2]}, hh[3] = {v.v[3], v.v[4], v.v[5]};
+            st_lds3(sE + 3 * k, e);
+            st_lds3(sH + 3 * k, hh);
+        });
     __syncthreads();
     const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
     if (tile >= a.tiles) return;
@@ -749,14 +797,19 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
     TC* sH = sE + 3 * (int64_t)a.hmax;
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
-    for (int k = threadIdx.x; k < hc; k += blockDim.x) {
-        const int j = a.hpool[h0 + k];
-        TC e[3], hh[3];
-        S::ld3(a.E, j, e[0], e[1], e[2]);
-        S::ld3(a.H, j, hh[0], hh[1], hh[2]);
-        st_lds3(sE + 3 * k, e);
-        st_lds3(sH + 3 * k, hh);
-    }
+    stage_rounds<4, Val6<TC>>(
+        a.hpool + h0, hc,
+        [&](int j) {
+            Val6<TC> v;
+            S::ld3(a.E, j, v.v[0], v.v[1], v.v[2]);
+            S::ld3(a.H, j, v.v[3], v.v[4], v.v[5]);
+            return v;
+        },
+        [&](int k, const Val6<TC>& v) {
+            const TC e[3] = {v.v[0], v.v[1], v.v[2]}, hh[3] = {v.v[3], v.v[4], v.v[5]};
+            st_lds3(sE + 3 * k, e);
+            st_lds3(sH + 3 * k, hh);
+        });
     __syncthreads();
     const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
     if (tile >= a.tiles) return;
@@ -827,11 +880,18 @@ template <typename TS>
 __device__ __forceinline__ void stage_vec3(const TS* F, const int32_t* list, int hc,
                                            typename Store<TS>::C* s) {
     using S = Store<TS>;
-    for (int k = threadIdx.x; k < hc; k += blockDim.x) {
-        typename S::C v[3];
-        S::ld3(F, list[k], v[0], v[1], v[2]);
-        st_lds3(s + 3 * k, v);
-    }
+    using TC = typename S::C;
+    stage_rounds<4, Val3<TC>>(
+        list, hc,
+        [&](int j) {
+            Val3<TC> v;
+            S::ld3(F, j, v.x, v.y, v.z);
+            return v;
+        },
+        [&](int k, const Val3<TC>& v) {
+            const TC w[3] = {v.x, v.y, v.z};
+            st_lds3(s + 3 * k, w);
+        });
 }
 
 // curl sums over the curl slots: d_x, d_y, d_z of the staged 3-vector field
