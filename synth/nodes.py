@@ -15,6 +15,10 @@ for it with the same spacing and irregularity:
   directions are filled in the same phase.
 * ``dual_grid_2d`` -- the jittered cell-centre grid used as the second node set
   of the two-set (staggered) variant.
+* ``poisson_disk_periodic`` / ``line_seeded_periodic`` -- the same dart
+  throwing on a periodic square around fixed seed points; with the seeds an
+  equispaced line this is the node set of the dispersion study (Section 6),
+  whose generator completes a discretised line y = L/2 into a scattered set.
 
 Boundary flags (uint8 per node): bit 0/1 = x low/high face, bit 2/3 = y, bit
 4/5 = z.  All random draws come from ``synth.rng`` keyed by (seed, stream,
@@ -184,3 +188,80 @@ def poisson_disk_2d(r, seed=2, stream=0, rounds=12):
     flags = np.concatenate([pf, np.zeros(n_int, np.uint8)])
     return xyz, flags, 1.0 / math.sqrt(xyz.shape[0])
 
+
+
+def poisson_disk_periodic(L, r, seeds, seed=3, stream=0, rounds=12):
+    """Poisson-disk-style nodes on the periodic square [0, L)^2 around seeds.
+
+    seeds [S, 2] are kept first, in order (they must be r apart, minimum
+    image); darts are accepted when they are at least r from every accepted
+    point, measured across the periodic wrap.  The cell grid has a multiple of
+    3 cells per side so that same-phase cells stay three apart across the wrap.
+    Returns xyz [N, 2] in [0, L)^2.
+    """
+    nc = 3 * int(math.ceil(L / (r / math.sqrt(2.0)) / 3.0))
+    cs = L / nc
+    seeds = np.asarray(seeds, dtype=np.float64).reshape(-1, 2) % L
+    occ = np.full((nc, nc), -1, dtype=np.int64)
+    cx = np.minimum((seeds[:, 0] / cs).astype(np.int64), nc - 1)
+    cy = np.minimum((seeds[:, 1] / cs).astype(np.int64), nc - 1)
+    if np.unique(cy * nc + cx).size != cx.size:
+        raise ValueError("two seeds share a cell: seeds must be at least r apart")
+    occ[cy, cx] = np.arange(seeds.shape[0])
+    allx = seeds[:, 0].copy()
+    ally = seeds[:, 1].copy()
+    r2 = r * r
+    gy, gx = np.meshgrid(np.arange(nc), np.arange(nc), indexing="ij")
+    gx = gx.reshape(-1)
+    gy = gy.reshape(-1)
+    counter = 0
+    for rnd in range(rounds):
+        for ph in range(9):
+            sel = ((gx % 3) == (ph % 3)) & ((gy % 3) == (ph // 3))
+            cxs = gx[sel]
+            cys = gy[sel]
+            empty = occ[cys, cxs] < 0
+            cxs = cxs[empty]
+            cys = cys[empty]
+            if cxs.size == 0:
+                continue
+            cid = (cys * nc + cxs).astype(np.uint64)
+            key = cid * np.uint64(2) + np.uint64(2 * nc * nc) * np.uint64(counter)
+            ux = rng.uniform(seed, stream, key)
+            uy = rng.uniform(seed, stream, key + np.uint64(1))
+            counter += 1
+            qx = np.minimum((cxs + ux) * cs, np.nextafter(L, 0.0))
+            qy = np.minimum((cys + uy) * cs, np.nextafter(L, 0.0))
+            ok = np.ones(qx.size, dtype=bool)
+            for dy in range(-2, 3):
+                for dx in range(-2, 3):
+                    j = occ[(cys + dy) % nc, (cxs + dx) % nc]
+                    has = j >= 0
+                    jj = np.where(has, j, 0)
+                    ddx = qx - allx[jj]
+                    ddy = qy - ally[jj]
+                    ddx -= L * np.round(ddx / L)
+                    ddy -= L * np.round(ddy / L)
+                    ok &= ~(has & (ddx * ddx + ddy * ddy < r2))
+            qx = qx[ok]
+            qy = qy[ok]
+            if qx.size == 0:
+                continue
+            start = allx.size
+            occ[cys[ok], cxs[ok]] = np.arange(start, start + qx.size)
+            allx = np.concatenate([allx, qx])
+            ally = np.concatenate([ally, qy])
+    return np.stack([allx, ally], axis=1)
+
+
+def line_seeded_periodic(L=200.0, h=1.0, r_factor=0.794, seed=3, stream=0, rounds=12):
+    """Scattered periodic nodes on [0, L)^2 that contain the equispaced line
+    y = L/2, x = 0, h, 2h, ... (Section 6): the L/h line nodes come first.
+
+    r = r_factor * h gives about one node per h^2 (the same density relation
+    as ``poisson_disk_2d``).  Returns (xyz [N, 2], flags zeros, h, line ids).
+    """
+    nl = int(round(L / h))
+    line = np.stack([np.arange(nl) * h, np.full(nl, 0.5 * L)], axis=1)
+    xyz = poisson_disk_periodic(L, r_factor * h, line, seed=seed, stream=stream, rounds=rounds)
+    return xyz, np.zeros(xyz.shape[0], np.uint8), h, np.arange(nl)

@@ -1,0 +1,155 @@
+"""Oracle pins for the dispersion measure of Section 6 (eq. 24-26).
+
+* Exact advection at the continuous speed: every peak lands on the wavenumber
+  nearest omega_j / S_c, so ||err||_1 equals its closed form (only the
+  quantisation of k is left).
+* A synthetic field with a known dispersion relation omega(k): the measured
+  wavenumbers are the ones omega(k) predicts.
+* A pulse moving towards -x lands in the upper half of the k axis.
+* A run of eq. 19 on a regular periodic grid: Appendix A gives its exact
+  numerical dispersion relation (the eigenphases of the amplification matrix
+  of eq. A.6), which predicts the measured peaks.
+"""
+import json
+import math
+import os
+
+import numpy as np
+
+from oracle import dispersion as D, knn, step, weights as W
+from synth import configs, nodes
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+RUN = GOLD["dispersion_run"]
+
+
+def _params():
+    nx, steps, every, jmax = RUN["Nx"], RUN["steps"], RUN["save_every"], RUN["jmax"]
+    nt = steps // every
+    assert nt == RUN["Nt"]
+    return nx, nt, every, jmax
+
+
+def _advected(nx, nt, every, speed, sigma=2.0, direction=1.0):
+    x = np.arange(nx, dtype=np.float64)
+    t = every * np.arange(1, nt + 1, dtype=np.float64)
+    out = np.zeros((nt, nx))
+    for img in range(-3, 4):
+        u = x[None, :] - 0.5 * nx - direction * speed * t[:, None] + img * nx
+        out += np.exp(-u * u / (2 * sigma * sigma))
+    return out
+
+
+def test_exact_advection_gives_the_quantisation_floor():
+    nx, nt, every, jmax = _params()
+    c0 = D.exact_speed()
+    total, err = D.err_l1(_advected(nx, nt, every, c0), every, jmax)
+    om = D.frequencies(nt, every)[1:jmax + 1]
+    dk = 2 * math.pi / nx
+    inear = np.rint(om / c0 / dk)
+    expect = np.abs(om / (inear * dk) - c0)
+    assert np.allclose(err, expect, rtol=0, atol=1e-15)
+    assert abs(total - expect.sum()) < 1e-13
+    assert total < 0.02
+
+
+def test_known_dispersion_relation_is_recovered():
+    nx, nt, every, jmax = _params()
+    c0 = D.exact_speed()
+    beta = 0.04
+    k = D.wavenumbers(nx)
+    om_k = c0 * k * (1 - beta * k * k)               # per step
+    x = np.arange(nx)
+    t = every * np.arange(1, nt + 1)
+    sig = 2.0
+    amp = np.exp(-(k * sig) ** 2 / 2)
+    samples = np.zeros((nt, nx))
+    for i in range(1, nx // 2):
+        samples += amp[i] * np.cos(k[i] * x[None, :] - om_k[i] * t[:, None])
+    idx, c = D.phase_speed(samples, every)
+    om = D.frequencies(nt, every)
+    dw = om[1]
+    checked = 0
+    for j in range(1, jmax + 1):
+        d = np.abs(om_k[1:nx // 2] - om[j]) / dw
+        order = np.argsort(d)
+        if d[order[0]] < 0.25 and d[order[1]] > 0.75:
+            assert idx[j] == order[0] + 1, j
+            assert abs(c[j] - om[j] / k[idx[j]]) < 1e-15
+            checked += 1
+    assert checked >= 10
+
+
+def test_direction_of_travel_sets_the_half_of_the_k_axis():
+    nx, nt, every, jmax = _params()
+    c0 = D.exact_speed()
+    right, _ = D.phase_speed(_advected(nx, nt, every, c0, direction=1.0), every)
+    left, _ = D.phase_speed(_advected(nx, nt, every, c0, direction=-1.0), every)
+    assert (right[1:jmax + 1] < nx // 2).all()
+    assert (left[1:jmax + 1] > nx // 2).all()
+
+
+def test_run_on_a_regular_grid_follows_appendix_a():
+    # periodic regular grid [0, 200) x [0, 8), h = 1, n = 13 (complete distance
+    # shells, so every node has the same stencil), no hyperviscosity: a plane
+    # wave e^{i k x} is an eigenfunction and one step multiplies its amplitudes
+    # by G(k) of eq. A.6, whose eigenphases theta(k) give omega(k) per step
+    nx, nt, every, jmax = _params()
+    ny = 8
+    gx, gy = np.meshgrid(np.arange(nx, dtype=np.float64), np.arange(ny, dtype=np.float64), indexing="xy")
+    xyz = np.stack([gx.reshape(-1), gy.reshape(-1)], 1)
+    P = (float(nx), float(ny))
+    idx = knn.knn(xyz, 13, period=P)
+    op = {"curl_idx": idx, "curl_w": W.curl_weights(xyz, xyz, idx, 2, period=P),
+          "hv_idx": idx, "hv_w": np.zeros(idx.shape)}
+    dt = configs.SC * 1.0
+    N = xyz.shape[0]
+    c0 = 1.0
+    # eq. 21 with sigma = 2: E at t = 0, Hy at t = -dt/2
+    def prof(t):
+        acc = np.zeros(N)
+        for img in range(-3, 4):
+            u = xyz[:, 0] - 0.5 * nx - c0 * t + img * nx
+            acc += np.exp(-u * u / 8.0)
+        return acc
+    E = prof(0.0)[:, None]
+    H = np.stack([np.zeros(N), -prof(-0.5 * dt)], 1)
+    line = np.arange(nx)                     # y = 0 row
+    rows = []
+    for s in range(nt * every):
+        H = step.h_update(E, H, op, dt, 0.0)
+        E = step.e_update(E, H, op, dt, 0.0, np.ones((N, 1)))
+        if (s + 1) % every == 0:
+            rows.append(E[line, 0].copy())
+    measured, _ = D.phase_speed(np.array(rows), every)
+    # Appendix A: amplification matrix of the plane wave e^{i k x} at node 0
+    d = knn.min_image(xyz[idx[0]] - xyz[0], P)
+    k = D.wavenumbers(nx)
+    theta = np.zeros(nx)
+    for i in range(1, nx // 2):
+        ph = np.exp(1j * k[i] * d[:, 0])
+        wx = (op["curl_w"][0, 0] * ph).sum()
+        wy = (op["curl_w"][0, 1] * ph).sum()
+        G = np.array([[1, 0, -dt * wy], [0, 1, dt * wx], [-dt * wy, dt * wx, 1 + dt * dt * (wx * wx + wy * wy)]])
+        lam = np.linalg.eigvals(G)
+        theta[i] = np.abs(np.angle(lam)).max()
+    om = D.frequencies(nt, every)
+    dw = om[1]
+    # candidates: the physical branch where the sigma = 2 pulse has its energy
+    # (near k = pi the discrete operator has a spurious branch with small
+    # theta that the pulse does not excite)
+    imax = 60
+    checked = 0
+    for j in range(1, jmax + 1):
+        dd = np.abs(theta[1:imax] - om[j]) / dw
+        order = np.argsort(dd)
+        assert measured[j] in (order[0] + 1, order[1] + 1), (j, measured[j], order[:2] + 1)
+        if dd[order[0]] < 0.25 and dd[order[1]] > 0.75:
+            assert measured[j] == order[0] + 1, (j, measured[j], order[0] + 1)
+            checked += 1
+    assert checked >= 10
+    # the regular-grid scheme propagates short waves faster than S_c, so the
+    # measured ||err||_1 exceeds the quantisation floor of exact advection
+    total, _ = D.err_l1(np.array(rows), every, jmax)
+    floor, _ = D.err_l1(_advected(nx, nt, every, D.exact_speed()), every, jmax)
+    assert total > floor

@@ -82,3 +82,24 @@ def test_workload_parameters():
     assert abs(w.steps * w.dt - np.sqrt(2)) < 1e-12
     w3 = configs.tm111_3d(n_side=6)
     assert w3.n_hv == 71 and w3.n == 35
+
+
+def test_line_seeded_periodic_nodes():
+    # Section 6 node set: the equispaced line y = L/2 comes first and unchanged,
+    # every pair of nodes is at least r apart across the periodic wrap, about
+    # one node per h^2, reproducible bit for bit
+    from synth import nodes as _n
+    L, h = 40.0, 1.0
+    xyz, flags, hh, line = _n.line_seeded_periodic(L, h, seed=7)
+    assert hh == h and (flags == 0).all()
+    assert np.array_equal(line, np.arange(40))
+    assert np.array_equal(xyz[:40, 0], np.arange(40.0)) and (xyz[:40, 1] == 20.0).all()
+    assert (xyz >= 0).all() and (xyz < L).all()
+    d = xyz[:, None, :] - xyz[None, :, :]
+    d -= L * np.round(d / L)
+    r2 = (d ** 2).sum(-1)
+    np.fill_diagonal(r2, np.inf)
+    assert r2.min() >= (0.794 * h) ** 2 * (1 - 1e-12)
+    assert 0.9 < xyz.shape[0] / (L * L) < 1.1
+    xyz2, _, _, _ = _n.line_seeded_periodic(L, h, seed=7)
+    assert np.array_equal(xyz, xyz2)
