@@ -511,6 +511,9 @@ def main():
                 wd = configs.dispersion_2d(n=nn, mode=mode)
                 sd = Solver.from_workload(wd, precision="f32")
                 sdt = sd.state(wd.E0, wd.H0)
+                if not args.no_tune:
+                    sd.autotune(sdt, reps=10)
+                    sdt = sd.state(wd.E0, wd.H0)
                 sd.run(sdt, 20, use_graph=True)
                 sdt = sd.state(wd.E0, wd.H0)
                 torch.cuda.synchronize()
