@@ -309,3 +309,67 @@ def test_periodic_pulse_paper_setup_on_gpu(mode):
     _announce(f"  vs oracle {e:.2e}; vs eq. 22: E {eE:.2e} H {eH:.2e}")
     assert e < 1e-10
     assert eE < 5e-4 and eH < 5e-4
+
+
+@pytest.mark.parametrize("shape", [(7, 7), (8, 8), (9, 8), (16, 16), (17, 16)])
+def test_tile_boundaries_small_sets(shape):
+    # node counts below one 64-node tile (49), exactly one (64), one more (72
+    # -> two tiles), one 256-node workgroup tile (256) and one more (272):
+    # order and stencils bit-exact, then 50 FP64 steps with oracle weights, in
+    # both the staged and the global kernels
+    _announce(f"small set {shape}")
+    xyz, flags, h = nodes.jittered_grid(shape, seed=41)
+    w = configs.Workload("small", 2, xyz, flags, h, 12, 2, 2, 31, 1e-3, 50)
+    w.E0, w.H0 = fields.gaussian_pulse(xyz, (0.5, 0.5), 0.2)
+    s = Solver.from_workload(w, precision="f64")
+    ns = max(w.n, w.n_hv)
+    ref = knn.knn(xyz, ns)
+    assert (_orig_stencils(s, s.stencils()) == ref).all()
+    oh, oe = osetup.operators(w)
+    _inject(s, oh)
+    Eo, Ho, _, _ = osetup.run_workload(w, oh, oe)
+    for lds in (1, 0):
+        s.set_variant(block=256, xcd=1, lds=lds)
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        eE = ostep.rel_l2(s.E_original(st), Eo)
+        eH = ostep.rel_l2(s.H_original(st), Ho)
+        _announce(f"  lds={lds} rel L2 E {eE:.2e} H {eH:.2e}")
+        assert eE < 1e-12 and eH < 1e-12
+
+
+def test_smallest_3d_set_two_partial_tiles():
+    # 5^3 = 125 nodes (n_hv = 71 needs at least 71): two partial 64-node tiles
+    _announce("3D 5^3 cube")
+    w = configs.tm111_3d(n_side=5, chat=1e-3, steps=20)
+    oh, oe = osetup.operators(w)
+    Eo, Ho, _, _ = osetup.run_workload(w, oh, oe)
+    s = Solver.from_workload(w, precision="f64")
+    _inject(s, oh)
+    for lds in (1, 0, 2):
+        s.set_variant(block=256, xcd=1, lds=lds)
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        e = max(ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho))
+        _announce(f"  lds={lds} rel L2 {e:.2e}")
+        assert e < 1e-12
+
+
+def test_batch_on_a_partial_tile():
+    # K = 8 fields on 49 nodes (less than one tile) against single-field runs
+    _announce("K = 8 batch on 49 nodes")
+    xyz, flags, h = nodes.jittered_grid((7, 7), seed=43)
+    w = configs.Workload("small", 2, xyz, flags, h, 12, 2, 2, 31, 1e-3, 40)
+    E0b = np.stack([fields.gaussian_pulse(xyz, (0.3 + 0.05 * k, 0.5), 0.2)[0] for k in range(8)])
+    sb = Solver.from_workload(w, precision="f32", K=8)
+    s1 = Solver.from_workload(w, precision="f32")
+    for lds in (1, 0):
+        sb.set_variant(block=256, xcd=1, lds=lds, persist=8)
+        stb = sb.state_batched(E0b, np.zeros((8, w.N, 2)))
+        sb.step(stb, w.steps)
+        Eb = sb.to_original(stb.E)[:, 0, :]
+        for k in (0, 7):
+            st = s1.state(E0b[k], np.zeros((w.N, 2)))
+            s1.step(st, w.steps)
+            e1 = s1.E_original(st)[:, 0]
+            assert np.abs(Eb[:, k] - e1).max() <= 1e-6 * np.abs(e1).max()
