@@ -199,6 +199,112 @@ __device__ __forceinline__ void stage_slice(const BLA& a, float* sm, int64_t til
     }
 }
 
+// One 4-slot chunk of a node's stencil: the halo values it reads from LDS
+// and its weights, all read before the chunk is summed so that the LDS reads
+// of a chunk are in flight together.
+struct HChunk {
+    f4 e[4], x[4], y[4];
+    f4 wx, wy, wh;
+};
+struct EChunk {
+    f4 hx[4], hy[4], e[4];
+    f4 wx, wy, wh;
+};
+
+template <int KSL>
+__device__ __forceinline__ const float* row(const float* sm, int k, int c, int fq) {
+    return sm + (k * 3 + c) * KSL + fq * 4;
+}
+
+template <int KSL>
+__device__ __forceinline__ void h_read(const BLA& a, const float* sm, uint4 lp, int q, int fq, const float* pc,
+                                       const float* ph, HChunk& c) {
+    const int hf = q & 1;
+    if (q < a.C4) {
+        c.wx = ldf4(pc + (q * 2 + 0) * RBFFD_TILE * 4);
+        c.wy = ldf4(pc + (q * 2 + 1) * RBFFD_TILE * 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c.e[u] = ldf4(row<KSL>(sm, posq(lp, hf, u), 0, fq));
+    }
+    if (q < a.V4) {
+        c.wh = ldf4(ph + q * RBFFD_TILE * 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = posq(lp, hf, u);
+            c.x[u] = ldf4(row<KSL>(sm, k, 1, fq));
+            c.y[u] = ldf4(row<KSL>(sm, k, 2, fq));
+        }
+    }
+}
+
+__device__ __forceinline__ void h_sum(const BLA& a, int q, const HChunk& c, const f4& e0, const f4& hx0, const f4& hy0,
+                                      f4& dx, f4& dy, f4& vx, f4& vy) {
+    if (q < a.C4) {
+        const float wxs[4] = {c.wx.x, c.wx.y, c.wx.z, c.wx.w}, wys[4] = {c.wy.x, c.wy.y, c.wy.z, c.wy.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            fma4(dx, wxs[u], c.e[u], e0);
+            fma4(dy, wys[u], c.e[u], e0);
+        }
+    }
+    if (q < a.V4) {
+        const float whs[4] = {c.wh.x, c.wh.y, c.wh.z, c.wh.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            fma4(vx, whs[u], c.x[u], hx0);
+            fma4(vy, whs[u], c.y[u], hy0);
+        }
+    }
+}
+
+template <int KSL>
+__device__ __forceinline__ void e_read(const BLA& a, const float* sm, uint4 lp, int q, int fq, const float* pc,
+                                       const float* ph, EChunk& c) {
+    const int hf = q & 1;
+    if (q < a.C4) {
+        c.wx = ldf4(pc + (q * 2 + 0) * RBFFD_TILE * 4);
+        c.wy = ldf4(pc + (q * 2 + 1) * RBFFD_TILE * 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = posq(lp, hf, u);
+            c.hx[u] = ldf4(row<KSL>(sm, k, 1, fq));
+            c.hy[u] = ldf4(row<KSL>(sm, k, 2, fq));
+        }
+    }
+    if (q < a.V4) {
+        c.wh = ldf4(ph + q * RBFFD_TILE * 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c.e[u] = ldf4(row<KSL>(sm, posq(lp, hf, u), 0, fq));
+    }
+}
+
+__device__ __forceinline__ void e_sum(const BLA& a, int q, const EChunk& c, const f4& e0, const f4& hx0, const f4& hy0,
+                                      f4& cu, f4& ve) {
+    if (q < a.C4) {
+        const float wxs[4] = {c.wx.x, c.wx.y, c.wx.z, c.wx.w}, wys[4] = {c.wy.x, c.wy.y, c.wy.z, c.wy.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            // curl H = D^dx Hy - D^dy Hx, in the single-field kernels' order
+            const f4& hx = c.hx[u];
+            const f4& hy = c.hy[u];
+            cu.x += wxs[u] * (hy.x - hy0.x) - wys[u] * (hx.x - hx0.x);
+            cu.y += wxs[u] * (hy.y - hy0.y) - wys[u] * (hx.y - hx0.y);
+            cu.z += wxs[u] * (hy.z - hy0.z) - wys[u] * (hx.z - hx0.z);
+            cu.w += wxs[u] * (hy.w - hy0.w) - wys[u] * (hx.w - hx0.w);
+        }
+    }
+    if (q < a.V4) {
+        const float whs[4] = {c.wh.x, c.wh.y, c.wh.z, c.wh.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) fma4(ve, whs[u], c.e[u], e0);
+    }
+}
+
+// positions of chunk pair m (chunks 2m, 2m + 1), zero past the last pair
+__device__ __forceinline__ uint4 pair_pos(const uint4* pl, int m, int npairs) {
+    return m < npairs ? pl[m * RBFFD_TILE] : make_uint4(0, 0, 0, 0);
+}
+
 template <int TPN>
 __global__ __launch_bounds__(RBFFD_WGT * TPN) void k_hbl(BLA a) {
     constexpr int KSL = 4 * TPN;          // fields per slice, 4 per thread
@@ -221,37 +327,20 @@ __global__ __launch_bounds__(RBFFD_WGT * TPN) void k_hbl(BLA a) {
     const float* pc = a.wc + (t64 * a.C4 * 2 * RBFFD_TILE + ln) * 4;
     const float* ph = a.wh + (t64 * a.V4 * RBFFD_TILE + ln) * 4;
     const int qm = max(a.C4, a.V4);
-    uint4 li = make_uint4(0, 0, 0, 0);
+    const int np = (qm + 1) >> 1;
+    uint4 lp = make_uint4(0, 0, 0, 0);
+    HChunk A;
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
-        const int hf = q & 1;
-        if (q < a.C4) {
-            const f4 wx = ldf4(pc + (q * 2 + 0) * RBFFD_TILE * 4), wy = ldf4(pc + (q * 2 + 1) * RBFFD_TILE * 4);
-            const float wxs[4] = {wx.x, wx.y, wx.z, wx.w}, wys[4] = {wy.x, wy.y, wy.z, wy.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const f4 e = ldf4(sm + (posq(li, hf, u) * 3 + 0) * KSL + fq * 4);
-                fma4(dx, wxs[u], e, e0);
-                fma4(dy, wys[u], e, e0);
-            }
-        }
-        if (q < a.V4) {
-            const f4 wh = ldf4(ph + q * RBFFD_TILE * 4);
-            const float whs[4] = {wh.x, wh.y, wh.z, wh.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = posq(li, hf, u);
-                fma4(vx, whs[u], ldf4(sm + (k * 3 + 1) * KSL + fq * 4), hx0);
-                fma4(vy, whs[u], ldf4(sm + (k * 3 + 2) * KSL + fq * 4), hy0);
-            }
-        }
+        if ((q & 1) == 0) lp = pair_pos(pl, q >> 1, np);
+        h_read<KSL>(a, sm, lp, q, fq, pc, ph, A);
+        h_sum(a, q, A, e0, hx0, hy0, dx, dy, vx, vy);
     }
-    const float A = a.a;
+    const float Af = a.a;
     const f4 G = ldf4(a.gk + k0);
-    stf4(a.out + (i * 2) * K + k0, {hx0.x + A * (-dy.x + G.x * vx.x), hx0.y + A * (-dy.y + G.y * vx.y),
-                                    hx0.z + A * (-dy.z + G.z * vx.z), hx0.w + A * (-dy.w + G.w * vx.w)});
-    stf4(a.out + (i * 2 + 1) * K + k0, {hy0.x + A * (dx.x + G.x * vy.x), hy0.y + A * (dx.y + G.y * vy.y),
-                                        hy0.z + A * (dx.z + G.z * vy.z), hy0.w + A * (dx.w + G.w * vy.w)});
+    stf4(a.out + (i * 2) * K + k0, {hx0.x + Af * (-dy.x + G.x * vx.x), hx0.y + Af * (-dy.y + G.y * vx.y),
+                                    hx0.z + Af * (-dy.z + G.z * vx.z), hx0.w + Af * (-dy.w + G.w * vx.w)});
+    stf4(a.out + (i * 2 + 1) * K + k0, {hy0.x + Af * (dx.x + G.x * vy.x), hy0.y + Af * (dx.y + G.y * vy.y),
+                                        hy0.z + Af * (dx.z + G.z * vy.z), hy0.w + Af * (dx.w + G.w * vy.w)});
 }
 
 template <int TPN>
@@ -276,38 +365,19 @@ __global__ __launch_bounds__(RBFFD_WGT * TPN) void k_ebl(BLA a) {
     const float* pc = a.wc + (t64 * a.C4 * 2 * RBFFD_TILE + ln) * 4;
     const float* ph = a.wh + (t64 * a.V4 * RBFFD_TILE + ln) * 4;
     const int qm = max(a.C4, a.V4);
-    uint4 li = make_uint4(0, 0, 0, 0);
+    const int np = (qm + 1) >> 1;
+    uint4 lp = make_uint4(0, 0, 0, 0);
+    EChunk A;
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) li = pl[(q >> 1) * RBFFD_TILE];
-        const int hf = q & 1;
-        if (q < a.C4) {
-            const f4 wx = ldf4(pc + (q * 2 + 0) * RBFFD_TILE * 4), wy = ldf4(pc + (q * 2 + 1) * RBFFD_TILE * 4);
-            const float wxs[4] = {wx.x, wx.y, wx.z, wx.w}, wys[4] = {wy.x, wy.y, wy.z, wy.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = posq(li, hf, u);
-                // curl H = D^dx Hy - D^dy Hx, in the single-field kernels' order
-                const f4 hx = ldf4(sm + (k * 3 + 1) * KSL + fq * 4);
-                const f4 hy = ldf4(sm + (k * 3 + 2) * KSL + fq * 4);
-                cu.x += wxs[u] * (hy.x - hy0.x) - wys[u] * (hx.x - hx0.x);
-                cu.y += wxs[u] * (hy.y - hy0.y) - wys[u] * (hx.y - hx0.y);
-                cu.z += wxs[u] * (hy.z - hy0.z) - wys[u] * (hx.z - hx0.z);
-                cu.w += wxs[u] * (hy.w - hy0.w) - wys[u] * (hx.w - hx0.w);
-            }
-        }
-        if (q < a.V4) {
-            const f4 wh = ldf4(ph + q * RBFFD_TILE * 4);
-            const float whs[4] = {wh.x, wh.y, wh.z, wh.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                fma4(ve, whs[u], ldf4(sm + (posq(li, hf, u) * 3 + 0) * KSL + fq * 4), e0);
-        }
+        if ((q & 1) == 0) lp = pair_pos(pl, q >> 1, np);
+        e_read<KSL>(a, sm, lp, q, fq, pc, ph, A);
+        e_sum(a, q, A, e0, hx0, hy0, cu, ve);
     }
-    const float A = a.a;
+    const float Af = a.a;
     const f4 G = ldf4(a.gk + k0);
     const bool keep = a.emask[i] & 1;
-    stf4(a.out + i * K + k0, keep ? f4{e0.x + A * (cu.x + G.x * ve.x), e0.y + A * (cu.y + G.y * ve.y),
-                                       e0.z + A * (cu.z + G.z * ve.z), e0.w + A * (cu.w + G.w * ve.w)}
+    stf4(a.out + i * K + k0, keep ? f4{e0.x + Af * (cu.x + G.x * ve.x), e0.y + Af * (cu.y + G.y * ve.y),
+                                       e0.z + Af * (cu.z + G.z * ve.z), e0.w + Af * (cu.w + G.w * ve.w)}
                                   : f4{0, 0, 0, 0});
 }
 
