@@ -136,7 +136,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip every leg after the headline one")
-    ap.add_argument("--legs", default="fp64,accuracy,batched,accuracy_alpha2,bf16,adjoint,stag2,hv_scan,dispersion,3d",
+    ap.add_argument("--legs", default="fp64,accuracy,batched,accuracy_alpha2,bf16,adjoint,stag2,hv_scan,dispersion,disk,3d",
                     help="comma-separated extra legs to run after the headline measurement")
     ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
@@ -549,6 +549,30 @@ def main():
             del sk, stk
         extras["dispersion"] = disp
         log(f"dispersion: {disp}")
+    if "disk" in legs:
+        # curved PEC wall: circular cavity with ~0.5M nodes, TM_01 mode, one
+        # period, FP32; error against the Bessel solution
+        from synth import fields as _fields
+        wk = configs.tm01_disk(h=0.0025)
+        sk, tk = setup_w(wk, "f32")
+        ak = sk.state(wk.E0, wk.H0)
+        if not args.no_tune:
+            sk.autotune(ak, reps=5)
+            ak = sk.state(wk.E0, wk.H0)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        sk.run(ak, wk.steps, use_graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tk2 = e0.elapsed_time(e1) * 1e-3
+        Ea, Ha, _ = _fields.tm01_disk(wk.xyz, wk.steps * wk.dt, (wk.steps - 0.5) * wk.dt)
+        Ek, Hk = sk.E_original(ak), sk.H_original(ak)
+        extras["tm01_disk"] = {"N": wk.N, "steps": wk.steps, "node_steps_per_s": wk.N * wk.steps / tk2,
+                               "linf_E_vs_bessel": float(np.abs(Ek - Ea).max()),
+                               "linf_H_vs_bessel": float(np.abs(Hk - Ha).max()), "setup_s": round(tk, 2)}
+        log(f"disk: {extras['tm01_disk']}")
+        del sk, ak
+        torch.cuda.empty_cache()
     if "3d" in legs:
         # 3D cube, 8.0M nodes, FP32 rate and FP32 vs FP64 over the workload's 2000 steps
         w3 = configs.tm111_3d(scale=1.0, chat=1e-3)

@@ -210,6 +210,20 @@ def dispersion_2d(n=60, mode="FD", L=200.0, h=1.0, sigma=2.0, chat=None, steps=2
     return w
 
 
+def tm01_disk(h=0.02, R=1.0, n=12, m=2, alpha=2, chat=1e-3, periods=1.0, seed=9):
+    """Circular PEC cavity (curved wall) with its TM_01 mode for ``periods``
+    periods; nodes from ``disk_nodes`` (equispaced on the circle, Poisson-disk
+    inside)."""
+    xyz, flags, hm = _nodes.disk_nodes(R, h, seed=seed)
+    w = Workload("tm01_disk", 2, xyz, flags, h, n, m, alpha, _hv_default(2, alpha), chat, 0,
+                 lo=(-R, -R), hi=(R, R))
+    E0, H0, om = _fields.tm01_disk(xyz, 0.0, -0.5 * w.dt, R=R)
+    w.E0, w.H0 = E0, H0
+    w.steps = int(round(periods * 2 * math.pi / om / w.dt))
+    w.meta.update(R=R, omega=om, h_mean=hm)
+    return w
+
+
 REGISTRY = {
     "tm_cavity_2d": tm_cavity_2d,
     "pulse_2d": pulse_2d,
@@ -218,6 +232,7 @@ REGISTRY = {
     "adjoint_2d": adjoint_2d,
     "periodic_pulse": periodic_pulse,
     "dispersion_2d": dispersion_2d,
+    "tm01_disk": tm01_disk,
 }
 
 

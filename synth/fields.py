@@ -134,3 +134,26 @@ def nearest_node(xyz, pts):
 def gaussian_wavelet(t, t0, tau):
     """Time profile of the soft source: exp(-(t - t0)^2 / (2 tau^2))."""
     return np.exp(-((np.asarray(t) - t0) ** 2) / (2.0 * tau * tau))
+
+
+def tm01_disk(xyz, t_e, t_h, R=1.0, centre=(0.0, 0.0), eps0=1.0, mu0=1.0):
+    """TM_01 mode of the circular PEC cavity of radius R (2D TMz).
+
+    Ez = J0(k r) cos(omega t), k = j_01 / R (first zero of J0), omega = c0 k;
+    Faraday's law gives H = (k / (mu0 omega)) J1(k r) (sin theta, -cos theta)
+    sin(omega t).  Returns (E [N, 1] at t_e, H [N, 2] at t_h, omega).
+    """
+    from scipy import special
+    c0, _ = consts(eps0, mu0)
+    k = special.jn_zeros(0, 1)[0] / R
+    om = c0 * k
+    dx = xyz[:, 0] - centre[0]
+    dy = xyz[:, 1] - centre[1]
+    r = np.hypot(dx, dy)
+    E = (special.j0(k * r) * math.cos(om * t_e))[:, None]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        st = np.where(r > 0, dy / np.where(r > 0, r, 1.0), 0.0)
+        ct = np.where(r > 0, dx / np.where(r > 0, r, 1.0), 0.0)
+    amp = k / (mu0 * om) * special.j1(k * r) * math.sin(om * t_h)
+    H = np.stack([amp * st, -amp * ct], axis=1)
+    return E, H, om

@@ -19,6 +19,8 @@ for it with the same spacing and irregularity:
   throwing on a periodic square around fixed seed points; with the seeds an
   equispaced line this is the node set of the dispersion study (Section 6),
   whose generator completes a discretised line y = L/2 into a scattered set.
+* ``disk_nodes`` -- a curved PEC boundary: equispaced nodes on a circle
+  (flagged as wall nodes) and Poisson-disk darts inside it.
 
 Boundary flags (uint8 per node): bit 0/1 = x low/high face, bit 2/3 = y, bit
 4/5 = z.  All random draws come from ``synth.rng`` keyed by (seed, stream,
@@ -265,3 +267,68 @@ def line_seeded_periodic(L=200.0, h=1.0, r_factor=0.794, seed=3, stream=0, round
     line = np.stack([np.arange(nl) * h, np.full(nl, 0.5 * L)], axis=1)
     xyz = poisson_disk_periodic(L, r_factor * h, line, seed=seed, stream=stream, rounds=rounds)
     return xyz, np.zeros(xyz.shape[0], np.uint8), h, np.arange(nl)
+
+
+def disk_nodes(R=1.0, h=0.02, centre=(0.0, 0.0), r_factor=0.794, seed=9, stream=0, rounds=12):
+    """Scattered nodes in the disk |x - centre| <= R with a curved wall.
+
+    The wall nodes are round(2 pi R / h) equispaced points on the circle
+    (flag FACE_XLO: in 2D any wall flag marks a node on which Ez vanishes);
+    interior darts inside the circle are accepted at least r = r_factor h
+    from every accepted node.  Returns (xyz [N, 2], flags [N], h_mean) with
+    h_mean = sqrt(pi R^2 / N).
+    """
+    cx, cy = float(centre[0]), float(centre[1])
+    nb = int(round(2.0 * math.pi * R / h))
+    th = 2.0 * math.pi * np.arange(nb) / nb
+    bx = cx + R * np.cos(th)
+    by = cy + R * np.sin(th)
+    r = r_factor * h
+    cs = r / math.sqrt(2.0)
+    nc = int(math.ceil(2.0 * R / cs)) + 1
+    x0, y0 = cx - R, cy - R
+    occ = np.full((nc + 4, nc + 4), -1, dtype=np.int64)
+    ix = np.minimum(((bx - x0) / cs).astype(np.int64), nc - 1)
+    iy = np.minimum(((by - y0) / cs).astype(np.int64), nc - 1)
+    occ[iy + 2, ix + 2] = np.arange(nb)
+    allx, ally = bx.copy(), by.copy()
+    r2 = r * r
+    gy, gx = np.meshgrid(np.arange(nc), np.arange(nc), indexing="ij")
+    gx = gx.reshape(-1)
+    gy = gy.reshape(-1)
+    counter = 0
+    for rnd in range(rounds):
+        for ph in range(9):
+            sel = ((gx % 3) == (ph % 3)) & ((gy % 3) == (ph // 3))
+            cxs, cys = gx[sel], gy[sel]
+            empty = occ[cys + 2, cxs + 2] < 0
+            cxs, cys = cxs[empty], cys[empty]
+            if cxs.size == 0:
+                continue
+            cid = (cys * nc + cxs).astype(np.uint64)
+            key = cid * np.uint64(2) + np.uint64(2 * nc * nc) * np.uint64(counter)
+            ux = rng.uniform(seed, stream, key)
+            uy = rng.uniform(seed, stream, key + np.uint64(1))
+            counter += 1
+            qx = x0 + (cxs + ux) * cs
+            qy = y0 + (cys + uy) * cs
+            ok = (qx - cx) ** 2 + (qy - cy) ** 2 < R * R
+            for dy in range(-2, 3):
+                for dx in range(-2, 3):
+                    j = occ[cys + 2 + dy, cxs + 2 + dx]
+                    has = j >= 0
+                    jj = np.where(has, j, 0)
+                    ddx = qx - allx[jj]
+                    ddy = qy - ally[jj]
+                    ok &= ~(has & (ddx * ddx + ddy * ddy < r2))
+            qx, qy = qx[ok], qy[ok]
+            if qx.size == 0:
+                continue
+            start = allx.size
+            occ[cys[ok] + 2, cxs[ok] + 2] = np.arange(start, start + qx.size)
+            allx = np.concatenate([allx, qx])
+            ally = np.concatenate([ally, qy])
+    xyz = np.stack([allx, ally], axis=1)
+    flags = np.zeros(xyz.shape[0], np.uint8)
+    flags[:nb] = FACE_XLO
+    return xyz, flags, math.sqrt(math.pi * R * R / xyz.shape[0])

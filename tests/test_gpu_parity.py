@@ -373,3 +373,34 @@ def test_batch_on_a_partial_tile():
             s1.step(st, w.steps)
             e1 = s1.E_original(st)[:, 0]
             assert np.abs(Eb[:, k] - e1).max() <= 1e-6 * np.abs(e1).max()
+
+
+def test_circular_cavity_curved_wall():
+    # TM_01 mode of the circular PEC cavity (5261 nodes, 1 1/8 periods, a phase
+    # at which E and H are both of order one): GPU with oracle weights (FP64),
+    # end to end (FP64, FP32) against the oracle, and against the Bessel
+    # solution
+    _announce("circular cavity TM_01")
+    w = configs.tm01_disk(h=0.025, periods=1.125)
+    oh, oe = osetup.operators(w)
+    Eo, Ho, _, _ = osetup.run_workload(w, oh, oe)
+    Ea, Ha, _ = fields.tm01_disk(w.xyz, w.steps * w.dt, (w.steps - 0.5) * w.dt)
+    eEo, eHo = ostep.linf_errors(Eo, Ho, Ea, Ha)
+    s = Solver.from_workload(w, precision="f64")
+    _inject(s, oh)
+    st = s.state(w.E0, w.H0)
+    s.step(st, w.steps)
+    e = max(ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho))
+    _announce(f"  injected f64 vs oracle {e:.2e}")
+    assert e < 1e-12
+    for prec, tol in (("f64", 1e-9), ("f32", 1e-5)):
+        s = Solver.from_workload(w, precision=prec)
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        E, H = s.E_original(st), s.H_original(st)
+        e = max(ostep.rel_l2(E, Eo), ostep.rel_l2(H, Ho))
+        eE, eH = ostep.linf_errors(E, H, Ea, Ha)
+        _announce(f"  {prec} vs oracle {e:.2e}; vs Bessel E {eE:.2e} (oracle {eEo:.2e}) H {eH:.2e} ({eHo:.2e})")
+        assert e < tol
+        assert (E[w.flags > 0] == 0).all()
+        assert eE < 1.05 * eEo + 1e-6 and eH < 1.05 * eHo + 1e-6

@@ -219,3 +219,20 @@ def test_amplification_eigenvalue_product_eq_A9():
         assert abs(rest[0] * rest[1] - GOLD["amplification_product"]["value"]) < 1e-12
         grew += np.abs(rest).max() > 1 + 1e-12
     assert grew > 0          # some scattered stencil amplifies (Appendix A)
+
+
+def test_tm01_circular_cavity_converges():
+    # a curved PEC wall: the TM_01 mode of a circular cavity (Ez = J0(j01 r / R)
+    # cos(omega t), closed form) after one period; Ez = 0 on the wall nodes
+    res = []
+    for h in (0.05, 0.025):
+        w = configs.tm01_disk(h=h)
+        oh, oe = setup.operators(w)
+        E, H, _, _ = setup.run_workload(w, oh, oe)
+        Ea, Ha, _ = fields.tm01_disk(w.xyz, w.steps * w.dt, (w.steps - 0.5) * w.dt)
+        assert np.abs(E[w.flags > 0]).max() == 0.0
+        res.append(step.linf_errors(E, H, Ea, Ha) + (w.meta["h_mean"],))
+    (eE1, eH1, h1), (eE2, eH2, h2) = res
+    assert eE1 < 1e-3 and eH1 < 2e-3
+    assert math.log(eE1 / eE2) / math.log(h1 / h2) >= 1.5
+    assert math.log(eH1 / eH2) / math.log(h1 / h2) >= 1.5
