@@ -101,6 +101,63 @@ def e_update(E, Hn, op, kappa, gamma, keep, src=None, rows=None):
     return out * keep
 
 
+# ---------------------------------------------------------------------------
+# 2D TEz polarisation (Hz, Ex, Ey): the same leapfrog and hyperviscosity with
+# the roles of the fields exchanged.  From the curl equations with the fields
+# (Ex, Ey, 0) and (0, 0, Hz):
+#   mu0 dHz/dt = -(dEy/dx - dEx/dy),  eps0 dEx/dt = dHz/dy,  eps0 dEy/dt = -dHz/dx,
+# so one step is
+#   Hz <- Hz - a (D^dx Ey - D^dy Ex - gamma D^hv Hz)
+#   Ex <- Ex + kappa (D^dy Hz_new + gamma D^hv Ex)
+#   Ey <- Ey + kappa (-D^dx Hz_new + gamma D^hv Ey)
+# with Hz^n = Hz(t_{n-1/2}) and a perfectly conducting wall zeroing the E
+# component tangential to it (Ey on x = const walls, Ex on y = const walls).
+# ---------------------------------------------------------------------------
+def te_h_update(E, Hz, op, a, gamma, rows=None):
+    """Hz^{n+1} [N, 1] from E^n = (Ex, Ey) [N, 2] and Hz^n [N, 1]."""
+    cw, ci = op["curl_w"], op["curl_idx"]
+    hw, hi = op["hv_w"], op["hv_idx"]
+    Hc = Hz if rows is None else Hz[rows]
+    curl = D(cw[:, 0], ci, E[:, 1]) - D(cw[:, 1], ci, E[:, 0])
+    return (Hc[:, 0] - a * (curl - gamma * D(hw, hi, Hz[:, 0])))[:, None]
+
+
+def te_e_update(E, Hz_new, op, kappa, gamma, keep, rows=None):
+    """E^{n+1} [N, 2] from E^n and Hz^{n+1}, then the PEC factors ``keep``."""
+    cw, ci = op["curl_w"], op["curl_idx"]
+    hw, hi = op["hv_w"], op["hv_idx"]
+    Ec = E if rows is None else E[rows]
+    h = Hz_new[:, 0]
+    Ex = Ec[:, 0] + kappa * (D(cw[:, 1], ci, h) + gamma * D(hw, hi, E[:, 0]))
+    Ey = Ec[:, 1] + kappa * (-D(cw[:, 0], ci, h) + gamma * D(hw, hi, E[:, 1]))
+    return np.stack([Ex, Ey], axis=1) * keep
+
+
+def pec_keep_te(flags):
+    """[N, 2] factors: a wall normal to x keeps only Ex, one normal to y only Ey."""
+    flags = np.asarray(flags)
+    keep = np.ones((flags.size, 2))
+    keep[(flags & 3) != 0, 1] = 0.0
+    keep[(flags & 12) != 0, 0] = 0.0
+    return keep
+
+
+def run_te(E, Hz, op, dt, steps, gamma, kappa, keep, mu0=1.0, eps0=1.0, h=None, energy_every=0):
+    """TEz counterpart of ``run``: returns (E, Hz, energies)."""
+    a = dt / mu0
+    eta0 = math.sqrt(mu0 / eps0)
+    E = np.array(E, dtype=np.float64)
+    Hz = np.array(Hz, dtype=np.float64)
+    energies = []
+    for n in range(steps):
+        Hn = te_h_update(E, Hz, op, a, gamma)
+        if energy_every and n % energy_every == 0:
+            energies.append(energy(E, Hz, Hn, h, h, eta0, 2))
+        E = te_e_update(E, Hn, op, kappa, gamma, keep)
+        Hz = Hn
+    return E, Hz, np.array(energies)
+
+
 def energy(E, H_old, H_new, h_e, h_h, eta0, dim):
     """U = h^d sum (|E|^2 + eta0^2 |(H_old + H_new)/2|^2) (eq. 20).
 

@@ -68,6 +68,7 @@ class Workload:
     flags_h: Optional[np.ndarray] = None
     h_h: Optional[float] = None
     # extras
+    pol: str = "TM"           # 2D polarisation: TM (Ez, Hx, Hy) | TE (Ex, Ey, Hz)
     K: int = 1
     E0_batch: Optional[np.ndarray] = None      # [K, N, FE]
     eps_r: Optional[np.ndarray] = None
@@ -120,6 +121,21 @@ def tm_cavity_2d(scale=1.0, n_side=None, seed=1, mode="FD", chat=1e-4, steps=Non
         w.xyz_h, w.flags_h, w.h_h = xh, fh, hh
         _, H, _ = _fields.tm_mode_2d(xh, 0.0, -0.5 * w.dt, eps0=eps0, mu0=mu0)
         w.H0 = H
+    return w
+
+
+def te_cavity_2d(scale=1.0, n_side=None, seed=1, mode="FD", chat=1e-3, steps=None, eps0=1.0, mu0=1.0,
+                 n=12, m=2, alpha=2, periods=1.0):
+    """TEz polarisation on the PEC unit square with its TE_11 mode (Hz at
+    half steps, E at whole steps) for ``periods`` periods."""
+    ns = n_side or max(8, int(round(50 * scale)) + 1)
+    xyz, flags, h = _nodes.jittered_grid((ns, ns), seed=seed)
+    w = Workload("te_cavity_2d", 2, xyz, flags, h, n, m, alpha, _hv_default(2, alpha),
+                 chat, 0, mode=mode, eps0=eps0, mu0=mu0, pol="TE")
+    w.steps = steps if steps is not None else int(round(periods * math.sqrt(2.0) / w.c0 / w.dt))
+    E, Hz, omega = _fields.te_mode_2d(xyz, 0.0, -0.5 * w.dt, eps0=eps0, mu0=mu0)
+    w.E0, w.H0 = E, Hz
+    w.meta["omega"] = omega
     return w
 
 
@@ -233,6 +249,7 @@ REGISTRY = {
     "periodic_pulse": periodic_pulse,
     "dispersion_2d": dispersion_2d,
     "tm01_disk": tm01_disk,
+    "te_cavity_2d": te_cavity_2d,
 }
 
 

@@ -36,6 +36,25 @@ def tm_mode_2d(xyz, t_e, t_h, m=1, n=1, eps0=1.0, mu0=1.0):
     return E, np.stack([Hx, Hy], axis=1), w
 
 
+def te_mode_2d(xyz, t_e, t_h, m=1, n=1, eps0=1.0, mu0=1.0):
+    """TE_mn mode of the PEC unit square: (Ex, Ey) at time t_e, Hz at t_h.
+
+    Hz = cos(m pi x) cos(n pi y) cos(omega t); Ampere's law gives
+    Ex = -(n pi / (eps0 omega)) cos(m pi x) sin(n pi y) sin(omega t) and
+    Ey = (m pi / (eps0 omega)) sin(m pi x) cos(n pi y) sin(omega t), which vanish
+    on the walls they are tangential to.
+    """
+    c0, _ = consts(eps0, mu0)
+    w = c0 * math.pi * math.hypot(m, n)
+    x, y = xyz[:, 0], xyz[:, 1]
+    sx, cx = np.sin(m * math.pi * x), np.cos(m * math.pi * x)
+    sy, cy = np.sin(n * math.pi * y), np.cos(n * math.pi * y)
+    Hz = (cx * cy * math.cos(w * t_h))[:, None]
+    Ex = -(n * math.pi / (eps0 * w)) * cx * sy * math.sin(w * t_e)
+    Ey = (m * math.pi / (eps0 * w)) * sx * cy * math.sin(w * t_e)
+    return np.stack([Ex, Ey], axis=1), Hz, w
+
+
 def tm111_cube(xyz, t_e, t_h, eps0=1.0, mu0=1.0):
     """TM_111 mode of the PEC unit cube: E at t_e, H at t_h."""
     c0, _ = consts(eps0, mu0)

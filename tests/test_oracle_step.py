@@ -3,8 +3,11 @@
 * One step on polynomial fields: the weights reproduce polynomials, so one
   step has a closed form (curl part and hyperviscosity part separately, 2D and
   3D, with eps0 != mu0 so that misplaced constants show).
-* Cavity modes (TM_11, TM_111) and the paper's periodic pulse (eq. 21-23):
-  errors against the analytic solutions fall as h falls.
+* Cavity modes (TM_11, TM_111, TE_11, and TM_01 of a circular cavity with a
+  curved wall) and the paper's periodic pulse (eq. 21-23): errors against the
+  analytic solutions fall as h falls.
+* The TEz polarisation is the Maxwell dual of TMz with the update order
+  swapped: checked exactly against the TMz functions.
 * Energy (eq. 20) stays bounded with hyperviscosity and blows up without it
   on scattered nodes (Section 5, Appendix A).
 * On a regular periodic grid one step maps a plane wave exactly as the
@@ -236,3 +239,46 @@ def test_tm01_circular_cavity_converges():
     assert eE1 < 1e-3 and eH1 < 2e-3
     assert math.log(eE1 / eE2) / math.log(h1 / h2) >= 1.5
     assert math.log(eH1 / eH2) / math.log(h1 / h2) >= 1.5
+
+
+def test_te_polarisation_is_the_dual_of_tm_with_the_update_order_swapped():
+    # Maxwell duality on a periodic set: with Hx = Ex, Hy = Ey, Ez = -Hz the
+    # TEz step (Hz from E, then E from the new Hz) is the TMz E update (with
+    # kappa = dt/mu0) followed by the TMz H update (with a = dt/eps0); eps0 !=
+    # mu0 so that exchanged constants show
+    xyz, flags, h = nodes.jittered_grid((17, 17), periodic=True, seed=13)
+    P = (1.0, 1.0)
+    op = _op(xyz, 12, 2, 31, 2, period=P)
+    N = xyz.shape[0]
+    eps0, mu0, dt = 2.0, 0.5, 0.004
+    g = step.hv_gamma(1e-3 / dt, 2, h)
+    E = np.stack([np.sin(2 * math.pi * xyz[:, 1]), np.cos(2 * math.pi * (xyz[:, 0] + xyz[:, 1]))], 1)
+    Hz = (np.cos(2 * math.pi * xyz[:, 0]) * np.sin(4 * math.pi * xyz[:, 1]))[:, None]
+    Ete, Hte = E.copy(), Hz.copy()
+    Htm, Etm = E.copy(), -Hz.copy()
+    keep = np.ones((N, 2))
+    for _ in range(40):
+        Hte = step.te_h_update(Ete, Hte, op, dt / mu0, g)
+        Ete = step.te_e_update(Ete, Hte, op, dt / eps0, g, keep)
+        Etm = step.e_update(Etm, Htm, op, dt / mu0, g, np.ones((N, 1)))
+        Htm = step.h_update(Etm, Htm, op, dt / eps0, g)
+    assert np.abs(Ete - Htm).max() < 1e-13 * np.abs(Htm).max()
+    assert np.abs(Hte + Etm).max() < 1e-13 * np.abs(Etm).max()
+
+
+def _te_cavity_err(ns):
+    w = configs.te_cavity_2d(n_side=ns, chat=1e-3, eps0=2.0, mu0=0.5)
+    oh, oe = setup.operators(w)
+    E, Hz, _, _ = setup.run_workload(w, oh, oe)
+    Ea, Ha, _ = fields.te_mode_2d(w.xyz, w.steps * w.dt, (w.steps - 0.5) * w.dt, eps0=2.0, mu0=0.5)
+    keep = step.pec_keep_te(w.flags)
+    assert (E[keep == 0] == 0).all()          # tangential E vanishes on the walls
+    return step.linf_errors(E, Hz, Ea, Ha), w.h
+
+
+def test_te11_cavity_converges():
+    (e1, m1), h1 = _te_cavity_err(26)
+    (e2, m2), h2 = _te_cavity_err(51)
+    assert e2 < 3e-4 and m2 < 3e-4
+    assert math.log(e1 / e2) / math.log(h1 / h2) >= 1.5
+    assert math.log(m1 / m2) / math.log(h1 / h2) >= 1.5
