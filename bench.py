@@ -136,7 +136,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip every leg after the headline one")
-    ap.add_argument("--legs", default="fp64,accuracy,batched,accuracy_alpha2,bf16,adjoint,stag2,hv_scan,dispersion,disk,3d",
+    ap.add_argument("--legs", default="fp64,accuracy,batched,accuracy_alpha2,bf16,adjoint,stag2,hv_scan,dispersion,disk,te,3d",
                     help="comma-separated extra legs to run after the headline measurement")
     ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
@@ -572,6 +572,30 @@ def main():
                                "linf_H_vs_bessel": float(np.abs(Hk - Ha).max()), "setup_s": round(tk, 2)}
         log(f"disk: {extras['tm01_disk']}")
         del sk, ak
+        torch.cuda.empty_cache()
+    if "te" in legs:
+        # TEz polarisation: TE_11 mode of the PEC square on a 1001^2 jittered
+        # grid (1.0M nodes, n = 12, n_hv = 31), one period, FP32
+        from synth import fields as _fields
+        wt = configs.te_cavity_2d(n_side=1001, chat=1e-3)
+        st_, tt = setup_w(wt, "f32")
+        at = st_.state(wt.E0, wt.H0)
+        if not args.no_tune:
+            st_.autotune(at, reps=5)
+            at = st_.state(wt.E0, wt.H0)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        st_.run(at, wt.steps, use_graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tte = e0.elapsed_time(e1) * 1e-3
+        Ea, Ha, _ = _fields.te_mode_2d(wt.xyz, wt.steps * wt.dt, (wt.steps - 0.5) * wt.dt)
+        extras["te_cavity"] = {"N": wt.N, "steps": wt.steps, "node_steps_per_s": wt.N * wt.steps / tte,
+                               "linf_E_vs_TE11": float(np.abs(st_.E_original(at) - Ea).max()),
+                               "linf_Hz_vs_TE11": float(np.abs(st_.H_original(at) - Ha).max()),
+                               "variant": st_.variant()}
+        log(f"te: {extras['te_cavity']}")
+        del st_, at
         torch.cuda.empty_cache()
     if "3d" in legs:
         # 3D cube, 8.0M nodes, FP32 rate and FP32 vs FP64 over the workload's 2000 steps

@@ -48,6 +48,16 @@ extern "C" {
                                  paper's choice; cross-set curl stencils)     */
 #define RBFFD_BC_PEC      0   /* perfectly conducting walls on flagged nodes  */
 #define RBFFD_BC_PERIODIC 1   /* periodic box [lo, hi) (minimum image)        */
+/* 2D polarisation.  TEz (Ex, Ey, Hz) uses the same leapfrog and
+ * hyperviscosity as TMz with the fields' roles exchanged:
+ *   Hz <- Hz - a (D^dx Ey - D^dy Ex - gamma D^hv Hz)
+ *   Ex <- Ex + kappa (D^dy Hz_new + gamma D^hv Ex)
+ *   Ey <- Ey + kappa (-D^dx Hz_new + gamma D^hv Ey)
+ * (Hz at half steps); a wall flagged as normal to x zeroes Ey, one normal to
+ * y zeroes Ex (axis-aligned walls).  Sources, receivers, the K-field batch,
+ * the adjoint and the two-set variant are TMz only. */
+#define RBFFD_POL_TM 0
+#define RBFFD_POL_TE 1
 #define RBFFD_ORDER_NONE   0
 #define RBFFD_ORDER_MORTON 1
 #define RBFFD_ORDER_RCM    2
@@ -73,7 +83,7 @@ extern "C" {
 /* ---- parameters -------------------------------------------------------- */
 /* Every parameter of the method (Section 4.3, Section 5, Section 5.1). */
 typedef struct rbffd_params {
-    int32_t dim;        /* 2 = TMz (Ez, Hx, Hy; eq. 3), 3 = full curl equations   */
+    int32_t dim;        /* 2 = TMz (eq. 3) or TEz (see pol), 3 = full curl eqs.  */
     int32_t mode;       /* RBFFD_MODE_*                                           */
     int32_t n;          /* curl stencil size (n nearest nodes, eq. 11)            */
     int32_t m;          /* curl monomial degree (eq. 8)                           */
@@ -86,7 +96,8 @@ typedef struct rbffd_params {
     int32_t fdtype;     /* field storage: F64, F32 or BF16 (BF16 needs F32 weights)*/
     int32_t K;          /* independent fields per batch (1 = single field; 2D)    */
     int32_t adjoint;    /* nonzero: also build transposed operators (2D, K = 1)   */
-    int32_t reserved;
+    int32_t pol;        /* 2D polarisation: RBFFD_POL_TM (Ez, Hx, Hy) or
+                           RBFFD_POL_TE (Ex, Ey, Hz; collocated, K = 1)           */
     double vfd_sigma;   /* RBF-VFD virtual spacing delta = vfd_sigma * h          */
     double hv_c;        /* c of gamma = c (-1)^(alpha-1) h^(2 alpha), units 1/time */
     double h;           /* nominal node spacing of the E set                      */
@@ -102,8 +113,9 @@ typedef struct rbffd_sizes {
     int64_t N_h;             /* nodes of the H set (= N when collocated)         */
     int32_t n_stencil;       /* collocated union stencil width max(n, n_hv)      */
     int32_t n_hv;            /* effective HV stencil size                        */
-    int32_t fe, fh;          /* values per node in E and H buffers (2D: 1, 2;
-                                3D: 4, 4 -- x, y, z and one unused pad value)    */
+    int32_t fe, fh;          /* values per node in E and H buffers (2D TMz: 1, 2;
+                                2D TEz: 2, 1; 3D: 4, 4 -- x, y, z and one unused
+                                pad value)                                       */
     int32_t field_elem;      /* bytes per stored field value (8, 4 or 2)         */
     int32_t K;
     int64_t arena_bytes;     /* persistent device arena (weights, stencils, ...) */

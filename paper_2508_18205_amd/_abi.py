@@ -19,7 +19,7 @@ class Params(C.Structure):
         ("dim", C.c_int32), ("mode", C.c_int32), ("n", C.c_int32), ("m", C.c_int32),
         ("phs_k", C.c_int32), ("hv_alpha", C.c_int32), ("n_hv", C.c_int32), ("bc", C.c_int32),
         ("reorder", C.c_int32), ("wdtype", C.c_int32), ("fdtype", C.c_int32), ("K", C.c_int32),
-        ("adjoint", C.c_int32), ("reserved", C.c_int32),
+        ("adjoint", C.c_int32), ("pol", C.c_int32),
         ("vfd_sigma", C.c_double), ("hv_c", C.c_double), ("h", C.c_double), ("h_h", C.c_double),
         ("dt", C.c_double), ("eps0", C.c_double), ("mu0", C.c_double),
         ("lo", C.c_double * 3), ("hi", C.c_double * 3),

@@ -186,6 +186,9 @@ extern "C" int rbffd_plan_create(const rbffd_params* prm, int64_t N, const doubl
         return fail(RBFFD_ENOTSUP, "K-field batches are implemented for collocated 2D FP32");
     if (q.adjoint && (q.dim != 2 || q.mode == RBFFD_MODE_STAG2 || q.K != 1 || q.fdtype == RBFFD_BF16))
         return fail(RBFFD_ENOTSUP, "the adjoint is implemented for collocated 2D, K = 1, F32/F64");
+    if (q.pol != RBFFD_POL_TM && q.pol != RBFFD_POL_TE) return fail(RBFFD_EINVAL, "pol must be TM or TE");
+    if (q.pol == RBFFD_POL_TE && (q.dim != 2 || q.mode == RBFFD_MODE_STAG2 || q.K != 1 || q.adjoint))
+        return fail(RBFFD_ENOTSUP, "the TEz polarisation is implemented for collocated 2D, K = 1, no adjoint");
     if (N < 1 || N > (int64_t)INT32_MAX / 2) return fail(RBFFD_ESIZE, "N out of range");
     for (int k = 0; k < q.dim; ++k)
         if (!(q.hi[k] > q.lo[k])) return fail(RBFFD_EINVAL, "hi must exceed lo on every axis");
@@ -219,10 +222,11 @@ extern "C" int rbffd_plan_create(const rbffd_params* prm, int64_t N, const doubl
         p->gamma = q.hv_c * p->hv_fac;
     }
     if (q.fdtype == RBFFD_F64 || q.fdtype == RBFFD_F32 || q.fdtype == RBFFD_BF16) {
-        p->fe_comp = q.dim == 2 ? 1 : 3;
-        p->fh_comp = q.dim == 2 ? 2 : 3;
-        p->FE = q.dim == 2 ? 1 : 4;
-        p->FH = q.dim == 2 ? 2 : 4;
+        const bool te = q.pol == RBFFD_POL_TE;
+        p->fe_comp = q.dim == 2 ? (te ? 2 : 1) : 3;
+        p->fh_comp = q.dim == 2 ? (te ? 1 : 2) : 3;
+        p->FE = q.dim == 2 ? (te ? 2 : 1) : 4;
+        p->FH = q.dim == 2 ? (te ? 1 : 2) : 4;
     }
     // Morton quantisation box: square, side = largest extent
     double side = 0;

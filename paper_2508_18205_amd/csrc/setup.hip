@@ -209,7 +209,7 @@ __global__ void k_relabel(const int32_t* knn_orig, int k, const int32_t* tperm, 
 }
 
 __global__ void k_internal_nodes(const double* xyz_in, const uint8_t* flags_in, const int32_t* perm, int64_t N, int d,
-                                 double* xyz, uint8_t* emask, int periodic) {
+                                 double* xyz, uint8_t* emask, int periodic, int te) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int64_t o = perm[p];
@@ -217,8 +217,12 @@ __global__ void k_internal_nodes(const double* xyz_in, const uint8_t* flags_in, 
     if (!emask) return;
     const uint8_t f = periodic ? 0 : flags_in[o];
     uint8_t keep;
-    if (d == 2) {
+    if (d == 2 && !te) {
         keep = f == 0 ? 1 : 0;              // Ez is tangential to every wall
+    } else if (d == 2) {
+        keep = 3;                           // (Ex, Ey): only the normal component survives
+        for (int k = 0; k < 2; ++k)
+            if (f & (3u << (2 * k))) keep &= (uint8_t)(1u << k);
     } else {
         keep = 7;
         for (int k = 0; k < 3; ++k)
@@ -986,7 +990,7 @@ int setup_nodes_and_stencils(rbffd_plan* p, void* wsp, hipStream_t st) {
         }
         hipLaunchKernelGGL(k_inverse, dim3(blocks(S.N)), dim3(256), 0, st, S.perm, S.N, S.inv);
         hipLaunchKernelGGL(k_internal_nodes, dim3(blocks(S.N)), dim3(256), 0, st, S.xyz_in, S.flags_in, S.perm, S.N, d,
-                           S.xyz, S.emask, (int)per);
+                           S.xyz, S.emask, (int)per, (int)(p->p.pol == RBFFD_POL_TE));
         return RBFFD_OK;
     };
     if (p->p.reorder == RBFFD_ORDER_RCM && !p->collocated)

@@ -43,6 +43,10 @@ struct SA {
     double dt, eps0;
     const void* eps_r;    // per-node eps_r (double for FP64 fields, else float) or null
     const uint8_t* emask;
+    // TEz: the 2D kernels with the fields' roles exchanged.  te = 1: the
+    // vector kernel updates (Ex, Ey) from Hz with factor -kappa_i and the wall
+    // mask; nomask = 1: the scalar kernel updates Hz (no wall mask)
+    int te, nomask;
     // LDS staging
     const uint4* lidx;    // [tiles][Q8][64] x 8 u16 halo positions
     const int32_t* hpool;
@@ -127,8 +131,18 @@ __global__ __launch_bounds__(512) void k_h2(SA<TS, TW> a) {
         }
     }
     if (i < a.N) {
-        const TC A = (TC)a.a, G = (TC)a.g;
-        S::st2(a.out, i, hx0 + A * (-dy + G * vx), hy0 + A * (dx + G * vy));
+        const TC G = (TC)a.g;
+        if (!a.te) {
+            const TC A = (TC)a.a;
+            S::st2(a.out, i, hx0 + A * (-dy + G * vx), hy0 + A * (dx + G * vy));
+        } else {
+            // TEz (Ex, Ey) <- E + kappa (D^dy Hz + gamma HV, -D^dx Hz + gamma HV),
+            // written as E - kappa (-D^dy Hz - gamma HV, D^dx Hz - gamma HV) with
+            // the host's gamma negated; then the wall mask
+            const TC A = -kappa_of(a, i);
+            const uint8_t m = a.emask[i];
+            S::st2(a.out, i, (m & 1) ? hx0 + A * (-dy + G * vx) : (TC)0, (m & 2) ? hy0 + A * (dx + G * vy) : (TC)0);
+        }
     }
 }
 
@@ -186,7 +200,7 @@ __global__ __launch_bounds__(512) void k_e2(SA<TS, TW> a) {
     }
     if (i < a.N) {
         const TC k = kappa_of(a, i);
-        const TC v = (a.emask[i] & 1) ? e0 + k * (cu + (TC)a.g * ve) : (TC)0;
+        const TC v = (a.nomask || (a.emask[i] & 1)) ? e0 + k * (cu + (TC)a.g * ve) : (TC)0;
         S::st1(a.out, i, v);
     }
 }
@@ -236,8 +250,18 @@ __global__ __launch_bounds__(512) void k_h2x(SA<TS, TW> a) {
         }
     }
     if (i < a.N) {
-        const TC A = (TC)a.a, G = (TC)a.g;
-        S::st2(a.out, i, hx0 + A * (-dy + G * vx), hy0 + A * (dx + G * vy));
+        const TC G = (TC)a.g;
+        if (!a.te) {
+            const TC A = (TC)a.a;
+            S::st2(a.out, i, hx0 + A * (-dy + G * vx), hy0 + A * (dx + G * vy));
+        } else {
+            // TEz (Ex, Ey) <- E + kappa (D^dy Hz + gamma HV, -D^dx Hz + gamma HV),
+            // written as E - kappa (-D^dy Hz - gamma HV, D^dx Hz - gamma HV) with
+            // the host's gamma negated; then the wall mask
+            const TC A = -kappa_of(a, i);
+            const uint8_t m = a.emask[i];
+            S::st2(a.out, i, (m & 1) ? hx0 + A * (-dy + G * vx) : (TC)0, (m & 2) ? hy0 + A * (dx + G * vy) : (TC)0);
+        }
     }
 }
 
@@ -279,7 +303,7 @@ __global__ __launch_bounds__(512) void k_e2x(SA<TS, TW> a) {
     }
     if (i < a.N) {
         const TC k = kappa_of(a, i);
-        const TC v = (a.emask[i] & 1) ? e0 + k * (cu + (TC)a.g * ve) : (TC)0;
+        const TC v = (a.nomask || (a.emask[i] & 1)) ? e0 + k * (cu + (TC)a.g * ve) : (TC)0;
         S::st1(a.out, i, v);
     }
 }
@@ -640,8 +664,18 @@ __global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
         }
     }
     if (i < a.N) {
-        const TC A = (TC)a.a, G = (TC)a.g;
-        S::st2(a.out, i, hx0 + A * (-dy + G * vx), hy0 + A * (dx + G * vy));
+        const TC G = (TC)a.g;
+        if (!a.te) {
+            const TC A = (TC)a.a;
+            S::st2(a.out, i, hx0 + A * (-dy + G * vx), hy0 + A * (dx + G * vy));
+        } else {
+            // TEz (Ex, Ey) <- E + kappa (D^dy Hz + gamma HV, -D^dx Hz + gamma HV),
+            // written as E - kappa (-D^dy Hz - gamma HV, D^dx Hz - gamma HV) with
+            // the host's gamma negated; then the wall mask
+            const TC A = -kappa_of(a, i);
+            const uint8_t m = a.emask[i];
+            S::st2(a.out, i, (m & 1) ? hx0 + A * (-dy + G * vx) : (TC)0, (m & 2) ? hy0 + A * (dx + G * vy) : (TC)0);
+        }
     }
 }
 
@@ -706,7 +740,7 @@ __global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
     }
     if (i < a.N) {
         const TC k = kappa_of(a, i);
-        const TC v = (a.emask[i] & 1) ? e0 + k * (cu + (TC)a.g * ve) : (TC)0;
+        const TC v = (a.nomask || (a.emask[i] & 1)) ? e0 + k * (cu + (TC)a.g * ve) : (TC)0;
         S::st1(a.out, i, v);
     }
 }
@@ -1212,6 +1246,18 @@ void launch_half(const rbffd_plan* p, bool hupd, const void* E, const void* H, v
     a.H = (const TS*)H;
     a.out = (TS*)out;
     a.eps_r = hupd ? nullptr : eps_r;
+    if (p->p.pol == RBFFD_POL_TE) {
+        // TEz: the Hz update runs the scalar (E-update) kernel on (Hz, E) and
+        // the E update the vector (H-update) kernel on (Hz_new, E); the
+        // scalar kernel's factor is -dt/mu0, both take -gamma
+        a.E = (const TS*)H;
+        a.H = (const TS*)E;
+        a.g = -p->gamma;
+        a.a = hupd ? -p->dt / p->p.mu0 : p->dt / p->p.eps0;
+        a.nomask = hupd ? 1 : 0;
+        a.te = hupd ? 0 : 1;
+        hupd = !hupd;
+    }
     if (p->collocated && o.hmax > 0 && p->var.lds) {
         using TC = typename Store<TS>::C;
         const dim3 grid((unsigned)o.nwg), block(RBFFD_WGT);
@@ -1385,6 +1431,8 @@ extern "C" int rbffd_run(const rbffd_plan* p, rbffd_fields* f, const rbffd_run_a
     if (a->T < 0) return set_err(p, RBFFD_EINVAL, "T < 0");
     hipStream_t st = (hipStream_t)stream;
     if (p->K > 1) return batched_run(p, f, a, ws, st);
+    if (p->p.pol == RBFFD_POL_TE && (a->n_src > 0 || a->n_rcv > 0))
+        return set_err(p, RBFFD_ENOTSUP, "sources and receivers are implemented for TMz");
     if (a->n_src > 0 && (!a->src_node || !a->src_amp || !a->src_wave))
         return set_err(p, RBFFD_EINVAL, "sources need node, amplitude and waveform arrays");
     if (a->n_rcv > 0 && (!a->rcv_node || !a->traces)) return set_err(p, RBFFD_EINVAL, "receivers need nodes and traces");

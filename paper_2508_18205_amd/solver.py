@@ -53,7 +53,7 @@ class Solver:
 
     def __init__(self, dim, xyz, flags, h, n, m, alpha, hv_c, lo, hi, *, n_hv=0, dt=0.0, mode="FD",
                  bc="PEC", eps0=1.0, mu0=1.0, vfd_sigma=0.5, phs_k=3, precision="f64", K=1,
-                 adjoint=False, reorder="MORTON", xyz_h=None, flags_h=None, h_h=0.0, device="cuda:0"):
+                 adjoint=False, reorder="MORTON", xyz_h=None, flags_h=None, h_h=0.0, pol="TM", device="cuda:0"):
         self.lib = _abi.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the rbffd library needs a GPU (no CPU path)")
@@ -67,6 +67,7 @@ class Solver:
         p.wdtype = 0 if precision == "f64" else 1
         p.fdtype = _abi.DTYPE[precision]
         p.K, p.adjoint = K, int(bool(adjoint))
+        p.pol = {"TM": 0, "TE": 1}[pol]
         p.vfd_sigma, p.hv_c, p.h, p.h_h, p.dt, p.eps0, p.mu0 = vfd_sigma, hv_c, h, h_h, dt, eps0, mu0
         for k in range(dim):
             p.lo[k], p.hi[k] = lo[k], hi[k]
@@ -94,8 +95,9 @@ class Solver:
         self.sizes = s
         self.N, self.NH = s.N, s.N_h
         self.FE, self.FH = s.fe, s.fh
-        self.fe = 1 if dim == 2 else 3
-        self.fh = 2 if dim == 2 else 3
+        self.pol = pol
+        self.fe = (2 if pol == "TE" else 1) if dim == 2 else 3
+        self.fh = (1 if pol == "TE" else 2) if dim == 2 else 3
         self.dt, self.gamma = s.dt, s.gamma
         with torch.cuda.device(self.device):
             self.arena = torch.empty(max(s.arena_bytes, 256), dtype=torch.uint8, device=self.device)
@@ -110,7 +112,8 @@ class Solver:
     @classmethod
     def from_workload(cls, w, precision="f64", **kw):
         args = dict(n_hv=w.n_hv, mode=w.mode, bc=w.bc, eps0=w.eps0, mu0=w.mu0, vfd_sigma=w.vfd_sigma,
-                    precision=precision, xyz_h=w.xyz_h, flags_h=w.flags_h, h_h=w.h_h or 0.0)
+                    precision=precision, xyz_h=w.xyz_h, flags_h=w.flags_h, h_h=w.h_h or 0.0,
+                    pol=getattr(w, "pol", "TM"))
         args.update(kw)
         return cls(w.dim, w.xyz, w.flags, w.h, w.n, w.m, w.alpha, w.hv_c, w.lo, w.hi, **args)
 

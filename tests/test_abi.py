@@ -84,3 +84,16 @@ def test_plan_validation_and_sizes_on_host():
                                    C.byref(plan))
         assert rc in (_abi.EINVAL, _abi.ESIZE, _abi.ENOTSUP), bad
     assert lib.rbffd_strerror(_abi.ESINGULAR) == b"singular local weight system"
+    # TEz polarisation: (Ex, Ey) and Hz per node; collocated 2D, K = 1 only
+    p = _params(_abi, pol=1)
+    assert lib.rbffd_plan_create(C.byref(p), xyz.shape[0], xyz.ctypes.data, flags.ctypes.data, 0, None, None,
+                                 C.byref(plan)) == 0
+    assert lib.rbffd_plan_sizes(plan, C.byref(s)) == 0
+    assert s.fe == 2 and s.fh == 1 and s.e_bytes == 121 * 2 * 8 and s.h_bytes == 121 * 8
+    lib.rbffd_plan_destroy(plan)
+    for bad, code in ((dict(pol=2), _abi.EINVAL), (dict(pol=1, K=4, fdtype=1, wdtype=1), _abi.ENOTSUP),
+                      (dict(pol=1, adjoint=1), _abi.ENOTSUP), (dict(pol=1, mode=2), _abi.ENOTSUP)):
+        p = _params(_abi, **bad)
+        rc = lib.rbffd_plan_create(C.byref(p), xyz.shape[0], xyz.ctypes.data, flags.ctypes.data, 0, None, None,
+                                   C.byref(plan))
+        assert rc == code, bad

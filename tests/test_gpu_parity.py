@@ -404,3 +404,54 @@ def test_circular_cavity_curved_wall():
         assert e < tol
         assert (E[w.flags > 0] == 0).all()
         assert eE < 1.05 * eEo + 1e-6 and eH < 1.05 * eHo + 1e-6
+
+
+def test_te_polarisation_cavity_and_periodic():
+    # TEz (Ex, Ey, Hz): TE_11 mode of the PEC square (51 x 51, 1 1/8 periods,
+    # a phase at which E and Hz are both of order one; eps0 != mu0) with
+    # oracle weights (FP64), end to end (FP64, FP32), both kernel families,
+    # the wall mask, and a periodic set
+    _announce("TEz cavity")
+    w = configs.te_cavity_2d(chat=1e-3, eps0=2.0, mu0=0.5, periods=1.125)
+    oh, oe = osetup.operators(w)
+    Eo, Ho, _, _ = osetup.run_workload(w, oh, oe)
+    Ea, Ha, _ = fields.te_mode_2d(w.xyz, w.steps * w.dt, (w.steps - 0.5) * w.dt, eps0=2.0, mu0=0.5)
+    eEo, eHo = ostep.linf_errors(Eo, Ho, Ea, Ha)
+    keep = ostep.pec_keep_te(w.flags)
+    s = Solver.from_workload(w, precision="f64")
+    assert s.fe == 2 and s.fh == 1
+    _inject(s, oh)
+    out = []
+    for lds in (1, 0):
+        s.set_variant(block=256, xcd=1, lds=lds)
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        out.append((s.E_original(st), s.H_original(st)))
+    assert (out[0][0] == out[1][0]).all() and (out[0][1] == out[1][1]).all()
+    e = max(ostep.rel_l2(out[0][0], Eo), ostep.rel_l2(out[0][1], Ho))
+    _announce(f"  injected f64 vs oracle {e:.2e}")
+    assert e < 1e-12
+    for prec, tol in (("f64", 1e-9), ("f32", 1e-5)):
+        s = Solver.from_workload(w, precision=prec)
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        E, H = s.E_original(st), s.H_original(st)
+        e = max(ostep.rel_l2(E, Eo), ostep.rel_l2(H, Ho))
+        eE, eH = ostep.linf_errors(E, H, Ea, Ha)
+        _announce(f"  {prec} vs oracle {e:.2e}; vs TE_11 E {eE:.2e} ({eEo:.2e}) Hz {eH:.2e} ({eHo:.2e})")
+        assert e < tol
+        assert (E[keep == 0] == 0).all()
+        assert eE < 1.05 * eEo + 1e-6 and eH < 1.05 * eHo + 1e-6
+    _announce("TEz periodic")
+    xyz, flags, h = nodes.jittered_grid((31, 31), periodic=True, seed=17)
+    wp = configs.Workload("te_periodic", 2, xyz, flags, h, 12, 2, 2, 31, 1e-3, 200, bc="PERIODIC", pol="TE")
+    wp.E0 = np.stack([np.sin(2 * math.pi * xyz[:, 1]), np.cos(2 * math.pi * xyz[:, 0])], 1)
+    wp.H0 = (np.cos(2 * math.pi * (xyz[:, 0] - xyz[:, 1])))[:, None]
+    ohp, oep = osetup.operators(wp)
+    Eo, Ho, _, _ = osetup.run_workload(wp, ohp, oep)
+    s = Solver.from_workload(wp, precision="f64")
+    st = s.state(wp.E0, wp.H0)
+    s.step(st, wp.steps)
+    e = max(ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho))
+    _announce(f"  periodic f64 vs oracle {e:.2e}")
+    assert e < 1e-9
