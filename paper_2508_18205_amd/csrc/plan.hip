@@ -396,7 +396,7 @@ extern "C" int rbffd_get_variant(const rbffd_plan* p, int32_t* v) {
 
 extern "C" int rbffd_set_variant(rbffd_plan* p, int32_t block, int32_t xcd, int32_t lds, int32_t persist) {
     if (!p) return RBFFD_EINVAL;
-    if (block < 64 || block > 512 || (block % 64) || persist < 1 || persist > 64 || lds < 0 || lds > 2)
+    if (block < 64 || block > 512 || (block % 64) || persist < 1 || persist > 64 || lds < 0 || lds > 3)
         return set_err(p, RBFFD_EINVAL, "bad launch variant");
     p->var.block = block;
     p->var.xcd = xcd ? 1 : 0;

@@ -316,7 +316,7 @@ def test_tile_boundaries_small_sets(shape):
     # node counts below one 64-node tile (49), exactly one (64), one more (72
     # -> two tiles), one 256-node workgroup tile (256) and one more (272):
     # order and stencils bit-exact, then 50 FP64 steps with oracle weights, in
-    # both the staged and the global kernels
+    # the staged, the global and the four-wavefronts-per-tile kernels
     _announce(f"small set {shape}")
     xyz, flags, h = nodes.jittered_grid(shape, seed=41)
     w = configs.Workload("small", 2, xyz, flags, h, 12, 2, 2, 31, 1e-3, 50)
@@ -328,7 +328,7 @@ def test_tile_boundaries_small_sets(shape):
     oh, oe = osetup.operators(w)
     _inject(s, oh)
     Eo, Ho, _, _ = osetup.run_workload(w, oh, oe)
-    for lds in (1, 0):
+    for lds in (1, 0, 3):
         s.set_variant(block=256, xcd=1, lds=lds)
         st = s.state(w.E0, w.H0)
         s.step(st, w.steps)
@@ -430,6 +430,12 @@ def test_te_polarisation_cavity_and_periodic():
     assert (out[0][0] == out[1][0]).all() and (out[0][1] == out[1][1]).all()
     e = max(ostep.rel_l2(out[0][0], Eo), ostep.rel_l2(out[0][1], Ho))
     _announce(f"  injected f64 vs oracle {e:.2e}")
+    assert e < 1e-12
+    s.set_variant(block=256, xcd=1, lds=3)
+    st = s.state(w.E0, w.H0)
+    s.step(st, w.steps)
+    e = max(ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho))
+    _announce(f"  four wavefronts per tile, f64 vs oracle {e:.2e}")
     assert e < 1e-12
     for prec, tol in (("f64", 1e-9), ("f32", 1e-5)):
         s = Solver.from_workload(w, precision=prec)
