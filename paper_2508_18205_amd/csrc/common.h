@@ -13,6 +13,8 @@
 #define RBFFD_TILE 64             // nodes per packed tile (one wavefront)
 #define RBFFD_WGT 256             // nodes per LDS-staged workgroup tile (4 wavefronts)
 #define RBFFD_LDS_BUDGET 65536    // bytes of LDS one staged workgroup may use
+#define RBFFD_LDS_BUDGET_3D 98304 // 3D: both operands together up to this size (fewer
+                                  // resident workgroups; the tuner also tries one at a time)
 #define RBFFD_KSLICE 16           // widest field slice of the staged K-field batch
 #define RBFFD_LDS_BUDGET_BATCH 122880
 

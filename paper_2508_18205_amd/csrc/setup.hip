@@ -1221,7 +1221,7 @@ int build_halos(rbffd_plan* p, void* wsp, hipStream_t st) {
             if ((((int64_t)mx + 3) / 4 * 4 + 2 * (int64_t)mx) * fb <= RBFFD_LDS_BUDGET) o.stage = 1;
         } else {
             // packed 3-vectors: both fields together, else one at a time
-            if (6 * (int64_t)mx * fb <= RBFFD_LDS_BUDGET) o.stage = 1;
+            if (6 * (int64_t)mx * fb <= RBFFD_LDS_BUDGET_3D) o.stage = 1;
             else if (3 * (int64_t)mx * fb <= RBFFD_LDS_BUDGET) o.stage = 2;
         }
         if (o.stage) o.hmax = mx;
