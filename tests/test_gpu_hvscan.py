@@ -3,7 +3,9 @@
 * Every field given the plan's c through rbffd_set_field_hv: bit-identical
   to the plain K-field run.
 * K fields, each with its own c, from one state: fields and per-field energy
-  series (eq. 20) against the FP64 oracle run with that c (FP32 tolerance).
+  series (eq. 20) against the FP64 oracle run with that c (FP32 tolerance:
+  1e-5, 1e-4 for the constants too small to stabilise the strip, whose
+  growing modes amplify the rounding).
 * rbffd_hv_scan against the oracle's search on the same periodic strip: the
   same candidates, energy ratios within FP32 tolerance (1e-4 for bounded
   runs; for growing runs 1% of the growth, which amplifies the rounding), the
@@ -94,9 +96,14 @@ def test_per_field_hv_and_energy_vs_oracle():
                  np.abs(Hb[:, :, k] - Ho).max() / np.abs(Ho).max())
         eu = np.abs(en[:, k] / en[0, k] - eno / eno[0]).max()
         e0 = abs(en[0, k] / eno[0] - 1)
+        _announce(f"  chat {chat[k]:.0e}: fields {ef:.2e}, energy {max(eu, e0):.2e}")
+        # below c dt = 1e-4 this strip has modes that grow by ~0.7 % per step
+        # (the spectral radius of the one-step matrix, oracle HV-search test):
+        # they amplify the FP32 rounding with their growth
+        tol = 1e-5 if chat[k] >= 1e-4 else 1e-4
+        assert ef < tol, (chat[k], ef)
         worst_f, worst_u = max(worst_f, ef), max(worst_u, eu, e0)
     _announce(f"  fields {worst_f:.2e}, energy {worst_u:.2e}")
-    assert worst_f < 1e-5
     assert worst_u < 1e-5
     # the same c in two slots gives identical results
     assert (Eb[:, 4] == Eb[:, 7]).all() and (en[:, 4] == en[:, 7]).all()
