@@ -1,6 +1,6 @@
 // The hot path: one fused kernel per half step of the stabilised leapfrog
 // (Kolar-Pozun & Kosec, arXiv 2508.18205, Section 5, eq. 19; 3D with the full
-// discrete curl), plus the run driver (sources, receivers, energy of eq. 20,
+// discrete curl), plus the step loop (sources, receivers, energy of eq. 20,
 // checkpoints, HIP-graph replay) and the FP64 reductions.
 //
 // Per node i the H update is
