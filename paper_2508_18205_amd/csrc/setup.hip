@@ -264,6 +264,7 @@ struct WArgs {
     int8_t ex[RBFFD_MAX_MONO][3];
     double* out;          // [Nt][nrhs][n]
     int64_t Nt;
+    int64_t c0;           // first centre of this launch
     int32_t* status;      // status[0] = first singular centre (atomicMin), status[1] = self-first violations
     int check_self;
 };
@@ -294,9 +295,9 @@ __device__ __forceinline__ double dmono_at0(const int8_t* e, int d, int axis) {
     return (deg == 1 && e[axis] == 1) ? 1.0 : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_weights(WArgs a) {
+__global__ __launch_bounds__(1024) void k_weights(WArgs a) {
     extern __shared__ double lds[];
-    const int64_t c = blockIdx.x;
+    const int64_t c = a.c0 + blockIdx.x;
     if (c >= a.Nt) return;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int n = a.n, M = a.M, R = n + M, d = a.d;
@@ -408,42 +409,51 @@ __global__ __launch_bounds__(256) void k_weights(WArgs a) {
     }
     __syncthreads();
 
-    // 3. forward elimination with partial pivoting
+    // 3. forward elimination with partial pivoting.  Rows are addressed
+    // through prm (logical row -> row of Am), so a pivot exchange is a swap of
+    // two entries; wavefront 0 picks the pivot (largest |value| in column k,
+    // ties to the lower logical row) and computes the multipliers, then every
+    // thread updates the trailing block: two barriers per column.
+    __shared__ int prm[RBFFD_MAX_STENCIL + RBFFD_MAX_MONO];
+    for (int i = tid; i < R; i += nt) prm[i] = i;
+    __syncthreads();
     for (int k = 0; k < R; ++k) {
         if (tid < 64) {
             double best = -1.0;
             int bi = R;
             for (int i = k + tid; i < R; i += 64) {
-                const double v = fabs(Am[i * lda + k]);
+                const double v = fabs(Am[prm[i] * lda + k]);
                 if (v > best) { best = v; bi = i; }
             }
             for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_down(best, off, 64);
-                const int oi = __shfl_down(bi, off, 64);
+                const double ob = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
                 if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
             }
+            // every lane now holds the pivot's logical row bi
+            const int rk = prm[k], rp = prm[bi];
+            if (!(best > 0.0)) {
+                if (tid == 0) s_bad = 1;
+            } else {
+                const double pk = Am[rp * lda + k];
+                // after the exchange logical row bi holds the old row k
+                for (int i = k + 1 + tid; i < R; i += 64) {
+                    const int ri = (i == bi) ? rk : prm[i];
+                    piv[i] = Am[ri * lda + k] / pk;
+                }
+            }
             if (tid == 0) {
-                s_p = bi;
-                if (!(best > 0.0)) s_bad = 1;
+                prm[bi] = rk;
+                prm[k] = rp;
             }
         }
         __syncthreads();
         if (s_bad) break;
-        const int p = s_p;
-        if (p != k)
-            for (int j = k + tid; j < lda; j += nt) {
-                const double t = Am[k * lda + j];
-                Am[k * lda + j] = Am[p * lda + j];
-                Am[p * lda + j] = t;
-            }
-        __syncthreads();
-        const double pk = Am[k * lda + k];
-        for (int i = k + 1 + tid; i < R; i += nt) piv[i] = Am[i * lda + k] / pk;
-        __syncthreads();
+        const int rk = prm[k];
         const int rows = R - k - 1, cols = lda - k - 1;
         for (int e = tid; e < rows * cols; e += nt) {
             const int i = k + 1 + e / cols, j = k + 1 + e % cols;
-            Am[i * lda + j] -= piv[i] * Am[k * lda + j];
+            Am[prm[i] * lda + j] -= piv[i] * Am[rk * lda + j];
         }
         __syncthreads();
     }
@@ -454,20 +464,21 @@ __global__ __launch_bounds__(256) void k_weights(WArgs a) {
     }
     // 4. back substitution, column by column of the unknowns
     for (int i = R - 1; i >= 0; --i) {
-        const double di = Am[i * lda + i];
-        for (int q = tid; q < a.nrhs; q += nt) Am[i * lda + R + q] /= di;
+        const int ri = prm[i];
+        const double di = Am[ri * lda + i];
+        for (int q = tid; q < a.nrhs; q += nt) Am[ri * lda + R + q] /= di;
         __syncthreads();
         for (int e = tid; e < i * a.nrhs; e += nt) {
-            const int r = e / a.nrhs, q = e % a.nrhs;
-            Am[r * lda + R + q] -= Am[r * lda + i] * Am[i * lda + R + q];
+            const int r = prm[e / a.nrhs], q = e % a.nrhs;
+            Am[r * lda + R + q] -= Am[r * lda + i] * Am[ri * lda + R + q];
         }
         __syncthreads();
     }
-    // 5. unscale and store the first n entries
+    // 5. unscale and store the first n entries (unknown j sits in row prm[j])
     const double us = ipow(sc, a.upow);
     for (int e = tid; e < a.nrhs * n; e += nt) {
         const int q = e / n, j = e % n;
-        a.out[c * a.nrhs * n + e] = Am[j * lda + R + q] / us;
+        a.out[c * a.nrhs * n + e] = Am[prm[j] * lda + R + q] / us;
     }
 }
 
@@ -1080,8 +1091,16 @@ static int launch_weights(rbffd_plan* p, const OpBlock& o, const NodeSet& T, con
         return set_err(p, RBFFD_ESIZE, "local system of " + std::to_string(R) + " unknowns needs " +
                                            std::to_string(lds) + " B of LDS; the device allows " +
                                            std::to_string(max_lds));
-    hipLaunchKernelGGL(k_weights, dim3((unsigned)o.Nt), dim3(256), lds, st, a);
-    HIPCHK(p, hipGetLastError());
+    // 16 wavefronts per system: the elimination steps are chains of LDS
+    // round trips, so more wavefronts hide more of their latency.  A dispatch
+    // counts its work-items in 32 bits, so at most 2^21 systems per launch.
+    constexpr int64_t chunk = (int64_t)1 << 21;
+    for (int64_t c0 = 0; c0 < o.Nt; c0 += chunk) {
+        a.c0 = c0;
+        const int64_t nb = std::min<int64_t>(chunk, o.Nt - c0);
+        hipLaunchKernelGGL(k_weights, dim3((unsigned)nb), dim3(1024), lds, st, a);
+        HIPCHK(p, hipGetLastError());
+    }
     return RBFFD_OK;
 }
 
