@@ -27,7 +27,7 @@ def operators(w, mode=None):
         ci = idx[:, :w.n]
         hi = idx[:, :w.n_hv]
         cw = _w.curl_weights(w.xyz, w.xyz, ci, w.m, mode=mode, sigma=w.vfd_sigma, h=w.h,
-                             period=period)
+                             period=period, frame_angle=w.frame_angle)
         hw = _w.hv_weights(w.xyz, w.xyz, hi, w.alpha, period=period)
         op = {"curl_idx": ci, "curl_w": cw, "hv_idx": hi, "hv_w": hw, "stencil": idx}
         return op, op
@@ -37,9 +37,11 @@ def operators(w, mode=None):
         hi_h = _knn.knn(XH, w.n_hv, period=period)
         ci_e = _knn.knn(XH, w.n, centres=XE, period=period)
         hi_e = _knn.knn(XE, w.n_hv, period=period)
-        op_h = {"curl_idx": ci_h, "curl_w": _w.curl_weights(XE, XH, ci_h, w.m, period=period),
+        op_h = {"curl_idx": ci_h, "curl_w": _w.curl_weights(XE, XH, ci_h, w.m, period=period,
+                                                           frame_angle=w.frame_angle),
                 "hv_idx": hi_h, "hv_w": _w.hv_weights(XH, XH, hi_h, w.alpha, period=period)}
-        op_e = {"curl_idx": ci_e, "curl_w": _w.curl_weights(XH, XE, ci_e, w.m, period=period),
+        op_e = {"curl_idx": ci_e, "curl_w": _w.curl_weights(XH, XE, ci_e, w.m, period=period,
+                                                           frame_angle=w.frame_angle),
                 "hv_idx": hi_e, "hv_w": _w.hv_weights(XE, XE, hi_e, w.alpha, period=period)}
         return op_h, op_e
     raise ValueError(mode)

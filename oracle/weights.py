@@ -18,6 +18,11 @@ For a centre x_c with stencil nodes x_j (j = 1..n):
     example of Section 4.2 prints the central-difference coefficients without
     the factor 1/2; the 1/2 is the only reading that reproduces d/dx x = 1 and
     is used here.
+  - Rotated frame (the angle study of Section 6, eq. 27): with a frame angle
+    theta the two derivatives are taken along u_1 = (cos theta, sin theta)
+    and u_2 = (-sin theta, cos theta) instead of e_x and e_y: RBF-FD
+    differentiates along u (b = u . grad of every basis function at 0) and
+    RBF-VFD places its virtual points at +-delta' u.
   - Hyperviscosity (Section 5.1): RBF-FD of the iterated Laplacian Delta^alpha
     with phi = r^(2 alpha + 1) and m = 2 alpha.
 * Unscaling: w = w_xi / s_c^l with l = 1 for first derivatives and 2 alpha for
@@ -166,6 +171,26 @@ def central_difference(d, axis):
     return (-0.5, 0.5), (-e, e)
 
 
+def frame_axes(d, theta):
+    """Unit vectors u_1, u_2 (rows) of the 2D frame at angle theta; the
+    identity for theta = 0 or in 3D (no rotated frame there)."""
+    if theta == 0.0 or d != 2:
+        return np.eye(d)
+    c, s = math.cos(theta), math.sin(theta)
+    return np.array([[c, s], [-s, c]])
+
+
+def fd_rhs_directional(xi, phs_k, exps, u):
+    """b for L = u . grad at xi = 0 (RBF-FD along the unit vector u)."""
+    b = None
+    for ax in range(xi.shape[2]):
+        if u[ax] == 0.0:
+            continue
+        t = u[ax] * fd_rhs_derivative(xi, phs_k, exps, ax)
+        b = t if b is None else b + t
+    return b
+
+
 def hv_rhs(xi, alpha, exps):
     """b for L = Delta^alpha with phi = r^(2 alpha + 1) at xi = 0."""
     d = xi.shape[2]
@@ -177,14 +202,17 @@ def hv_rhs(xi, alpha, exps):
 
 
 def curl_weights(src, centres, idx, m, phs_k=3, mode="FD", sigma=0.5, h=None,
-                 period=None, batch=4096):
+                 period=None, batch=4096, frame_angle=0.0):
     """First-derivative weights [C, d, n] (axis-major) for every centre.
 
     mode "FD" = RBF-FD (eq. 13); "VFD" = RBF-VFD (eq. 15) with delta = sigma h.
+    frame_angle (2D): derivatives along the axes of the frame rotated by that
+    angle (axis 0 along u_1, axis 1 along u_2).
     """
     d = src.shape[1]
     exps = monomial_exponents(d, m)
     C, n = idx.shape
+    U = frame_axes(d, frame_angle)
     W = np.empty((C, d, n))
     for b0 in range(0, C, batch):
         sl = slice(b0, min(C, b0 + batch))
@@ -193,10 +221,9 @@ def curl_weights(src, centres, idx, m, phs_k=3, mode="FD", sigma=0.5, h=None,
         cols = []
         for ax in range(d):
             if mode == "FD":
-                cols.append(fd_rhs_derivative(xi, phs_k, exps, ax))
+                cols.append(fd_rhs_directional(xi, phs_k, exps, U[ax]))
             elif mode == "VFD":
-                cf, off = central_difference(d, ax)
-                cols.append(vfd_rhs(xi, phs_k, exps, cf, off, sigma * h / s, 1))
+                cols.append(vfd_rhs(xi, phs_k, exps, (-0.5, 0.5), (-U[ax], U[ax]), sigma * h / s, 1))
             else:
                 raise ValueError(mode)
         B = np.stack(cols, axis=2)

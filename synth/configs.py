@@ -69,6 +69,7 @@ class Workload:
     h_h: Optional[float] = None
     # extras
     pol: str = "TM"           # 2D polarisation: TM (Ez, Hx, Hy) | TE (Ex, Ey, Hz)
+    frame_angle: float = 0.0  # 2D: angle of the frame the curl is discretised in
     K: int = 1
     E0_batch: Optional[np.ndarray] = None      # [K, N, FE]
     eps_r: Optional[np.ndarray] = None
@@ -205,11 +206,17 @@ def periodic_pulse(h=1.0, Ly=None, sigma=30.0, seed=6, chat=1e-4, mode="FD", n=1
 
 
 def dispersion_2d(n=60, mode="FD", L=200.0, h=1.0, sigma=2.0, chat=None, steps=2820, save_every=15,
-                  seed=3, m=2, alpha=2):
+                  seed=3, m=2, alpha=2, phi=0.0):
     """The dispersion study of Section 6: periodic [0, L)^2 with a scattered
     node set that contains the equispaced line y = L/2 (node ids 0..L/h-1),
     the narrow pulse of eq. 21 (sigma = 2), 2820 steps (one passage across the
     domain), E sampled on the line every ``save_every`` steps.
+
+    phi: propagation angle of the angle study (eq. 27).  The domain and the
+    seeded line are those of phi = 0 seen from coordinates rotated by -phi:
+    the pulse runs along the line, and the curl is discretised in the frame
+    at angle -phi to the domain (the x and y axes of eq. 27), where H has the
+    components (sin phi, -cos phi) g / eta0.
 
     chat defaults to the paper's hyperviscosity constants for this setup,
     c = 10^-4.76 (RBF-FD) and 10^-5.02 (RBF-VFD) in units h = dt = 1, i.e.
@@ -219,10 +226,11 @@ def dispersion_2d(n=60, mode="FD", L=200.0, h=1.0, sigma=2.0, chat=None, steps=2
         chat = 10.0 ** (-4.76 if mode == "FD" else -5.02)
     xyz, flags, hh, line = _nodes.line_seeded_periodic(L, h, seed=seed)
     w = Workload("dispersion_2d", 2, xyz, flags, hh, n, m, alpha, _hv_default(2, alpha), chat, steps,
-                 mode=mode, bc="PERIODIC", lo=(0.0, 0.0), hi=(L, L))
-    w.E0, w.H0 = _fields.periodic_plane_pulse(xyz, 0.0, -0.5 * w.dt, L=L, sigma=sigma)
+                 mode=mode, bc="PERIODIC", lo=(0.0, 0.0), hi=(L, L), frame_angle=-phi)
+    E0, H0 = _fields.periodic_plane_pulse(xyz, 0.0, -0.5 * w.dt, L=L, sigma=sigma)
+    w.E0, w.H0 = E0, (_fields.in_frame(H0, -phi) if phi != 0.0 else H0)
     w.rcv_node = line
-    w.meta.update(sigma=sigma, L=L, save_every=save_every, line=line)
+    w.meta.update(sigma=sigma, L=L, save_every=save_every, line=line, phi=phi)
     return w
 
 

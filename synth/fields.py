@@ -111,6 +111,13 @@ def periodic_plane_pulse(xyz, t_e, t_h, L=200.0, sigma=30.0, phi=0.0, eps0=1.0,
     return E, H
 
 
+def in_frame(H, theta):
+    """Components of the 2D vectors H [N, 2] in the frame with axes
+    u_1 = (cos theta, sin theta), u_2 = (-sin theta, cos theta)."""
+    c, s = math.cos(theta), math.sin(theta)
+    return np.stack([c * H[:, 0] + s * H[:, 1], -s * H[:, 0] + c * H[:, 1]], axis=1)
+
+
 def eps_r_smooth(xyz, seed=5, stream=2, n_modes=16, kmax=4, amp=0.5):
     """eps_r = 1 + amp * s(x) / max|s|, s = sum of 16 seeded cosine modes.
 

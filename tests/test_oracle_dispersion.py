@@ -153,3 +153,25 @@ def test_run_on_a_regular_grid_follows_appendix_a():
     total, _ = D.err_l1(np.array(rows), every, jmax)
     floor, _ = D.err_l1(_advected(nx, nt, every, D.exact_speed()), every, jmax)
     assert total > floor
+
+
+def _line_traces(mode, phi, L=24.0, steps=80):
+    from oracle import setup as osetup
+    w = configs.dispersion_2d(n=13, mode=mode, L=L, steps=steps, chat=1e-4, phi=phi)
+    oh, oe = osetup.operators(w)
+    _, _, _, tr = osetup.run_workload(w, oh, oe)
+    return tr
+
+
+def test_angle_study_rbffd_is_independent_of_the_frame():
+    # eq. 27: the pulse along the line with the curl discretised in the frame
+    # at angle -phi.  RBF-FD differentiates along any direction by the same
+    # rotation of its weights, the discrete curl and the isotropic
+    # hyperviscosity commute with that rotation, so E on the line is the same
+    # for every phi (to rounding); RBF-VFD's virtual points break the symmetry.
+    phi = math.pi / 5
+    for mode, same in (("FD", True), ("VFD", False)):
+        t0 = _line_traces(mode, 0.0)
+        t1 = _line_traces(mode, phi)
+        dev = np.abs(t1 - t0).max() / np.abs(t0).max()
+        assert (dev < 1e-11) if same else (dev > 1e-6), (mode, dev)

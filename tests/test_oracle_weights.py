@@ -201,3 +201,46 @@ def test_truncation_order(op, nm, slope):
     e2, h2 = _max_interior_err(81, nm, op)
     p = math.log(e1 / e2) / math.log(h1 / h2)
     assert p >= slope, p
+
+
+def _rot(theta):
+    c, s = math.cos(theta), math.sin(theta)
+    return np.array([[c, -s], [s, c]])
+
+
+@pytest.mark.parametrize("mode", ["FD", "VFD"])
+def test_rotated_frame_weights_are_rotation_covariant(mode):
+    # Weights depend only on the geometry relative to the differentiation
+    # direction: differentiating along u_1 = R(theta) e_x on nodes X equals
+    # differentiating along e_x on the nodes R(-theta) X (PHS is radial, the
+    # polynomial space is closed under rotation, the virtual points turn with u).
+    xyz, _, h, idx = _stencils((9, 9), 13)
+    theta = 0.7
+    wr = W.curl_weights(xyz, xyz, idx, 2, mode=mode, h=h, frame_angle=theta)
+    y = xyz @ _rot(-theta).T
+    w0 = W.curl_weights(y, y, idx, 2, mode=mode, h=h)
+    assert np.abs(wr - w0).max() <= 1e-9 * np.abs(w0).max()
+    # and the frame is a genuine rotation of the unrotated weights for RBF-FD
+    # only: the virtual points of RBF-VFD do not turn with the frame otherwise
+    wx = W.curl_weights(xyz, xyz, idx, 2, mode=mode, h=h)
+    lin = np.stack([math.cos(theta) * wx[:, 0] + math.sin(theta) * wx[:, 1],
+                    -math.sin(theta) * wx[:, 0] + math.cos(theta) * wx[:, 1]], axis=1)
+    dev = np.abs(wr - lin).max() / np.abs(w0).max()
+    assert (dev <= 1e-9) if mode == "FD" else (dev > 1e-6)
+
+
+@pytest.mark.parametrize("mode,deg", [("FD", 2), ("VFD", 2)])
+def test_rotated_frame_directional_reproduction(mode, deg):
+    # sum_j w_j p(x_j) = u . grad p (x_c) for every monomial of degree <= deg
+    xyz, _, h, idx = _stencils((9, 9), 13)
+    theta = -0.45
+    wr = W.curl_weights(xyz, xyz, idx, 2, mode=mode, h=h, frame_angle=theta)
+    u = np.array([[math.cos(theta), math.sin(theta)], [-math.sin(theta), math.cos(theta)]])
+    for e in W.monomial_exponents(2, deg):
+        for c in range(0, xyz.shape[0], 5):
+            vals = _mono_shift(xyz[idx[c]], xyz[c], e)
+            for ax in range(2):
+                expect = sum(u[ax, k] * _dmono_at_centre(e, k) for k in range(2))
+                got = (wr[c, ax] * vals).sum()
+                scale = np.abs(wr[c, ax] * vals).sum() + 1.0
+                assert abs(got - expect) <= 1e-9 * scale
