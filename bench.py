@@ -528,6 +528,22 @@ def main():
                                          "u_min": float(np.nanmin(u)), "u_max": float(np.nanmax(u)),
                                          "node_steps_per_s": wd.N * wd.steps / td}
                 del sd, sdt
+        # angle study (eq. 27, Figure 12): the curl in the frame turned by
+        # -phi, n = 60, phi from 0 to pi/4
+        for mode in ("FD", "VFD"):
+            row = {}
+            for q in range(5):
+                phi = q * math.pi / 16
+                wd = configs.dispersion_2d(n=60, mode=mode, phi=phi)
+                sd = Solver.from_workload(wd, precision="f32")
+                sdt = sd.state(wd.E0, wd.H0)
+                rd = sd.run(sdt, wd.steps, energy_every=20, rcv=wd.rcv_node, use_graph=True)
+                tr = rd["traces"].double().cpu().numpy()[wd.meta["save_every"] - 1::wd.meta["save_every"]]
+                u = rd["energy"] / rd["energy"][0]
+                row[f"{q}pi/16"] = {"err_l1": dispersion_l1(tr, wd.meta["save_every"]),
+                                    "u_min": float(np.nanmin(u)), "u_max": float(np.nanmax(u))}
+                del sd, sdt
+            disp[f"angle_{mode}_n60"] = row
         wd = configs.dispersion_2d(n=60, mode="FD")
         disp["N"] = wd.N
         disp["chat"] = {"FD": 10 ** -4.76, "VFD": 10 ** -5.02}

@@ -105,6 +105,13 @@ typedef struct rbffd_params {
     double dt;          /* time step; 0 = h / (10 sqrt(2) c0)                     */
     double eps0, mu0;   /* vacuum constants (c0 = 1/sqrt(eps0 mu0))               */
     double lo[3], hi[3];/* bounding box; the period for RBFFD_BC_PERIODIC         */
+    double frame_angle; /* 2D only (0 in 3D): angle theta of the frame the curl is
+                           discretised in (the angle study of Section 6, eq. 27).
+                           The two derivative operators act along
+                           u1 = (cos theta, sin theta), u2 = (-sin theta, cos
+                           theta), and field vectors are stored in components
+                           along u1, u2; RBF-VFD puts its virtual points at
+                           +-delta u.  0 = the x and y axes.                     */
 } rbffd_params;
 
 /* Sizes of every caller-owned buffer, in bytes, plus derived constants. */

@@ -22,7 +22,7 @@ class Params(C.Structure):
         ("adjoint", C.c_int32), ("pol", C.c_int32),
         ("vfd_sigma", C.c_double), ("hv_c", C.c_double), ("h", C.c_double), ("h_h", C.c_double),
         ("dt", C.c_double), ("eps0", C.c_double), ("mu0", C.c_double),
-        ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+        ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("frame_angle", C.c_double),
     ]
 
 

@@ -189,6 +189,10 @@ extern "C" int rbffd_plan_create(const rbffd_params* prm, int64_t N, const doubl
     if (q.pol != RBFFD_POL_TM && q.pol != RBFFD_POL_TE) return fail(RBFFD_EINVAL, "pol must be TM or TE");
     if (q.pol == RBFFD_POL_TE && (q.dim != 2 || q.mode == RBFFD_MODE_STAG2 || q.K != 1 || q.adjoint))
         return fail(RBFFD_ENOTSUP, "the TEz polarisation is implemented for collocated 2D, K = 1, no adjoint");
+    if (!std::isfinite(q.frame_angle) || (q.dim != 2 && q.frame_angle != 0.0))
+        return fail(RBFFD_EINVAL, "frame_angle must be finite, and 0 unless dim = 2");
+    if (q.frame_angle != 0.0 && q.pol == RBFFD_POL_TE && q.bc == RBFFD_BC_PEC)
+        return fail(RBFFD_ENOTSUP, "TEz walls are axis-aligned: a rotated frame needs periodic boundaries");
     if (N < 1 || N > (int64_t)INT32_MAX / 2) return fail(RBFFD_ESIZE, "N out of range");
     for (int k = 0; k < q.dim; ++k)
         if (!(q.hi[k] > q.lo[k])) return fail(RBFFD_EINVAL, "hi must exceed lo on every axis");

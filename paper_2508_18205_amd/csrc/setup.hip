@@ -259,6 +259,7 @@ struct WArgs {
     int periodic;
     double period[3];
     double vdelta;        // RBF-VFD virtual spacing (unscaled)
+    double fu[3][3];      // derivative directions: right-hand side q acts along fu[q]
     double hv_C;          // Delta^alpha r^(2a+1) = hv_C r
     double hv_poly[RBFFD_MAX_MONO];
     int8_t ex[RBFFD_MAX_MONO][3];
@@ -289,10 +290,14 @@ __device__ __forceinline__ double mono(const double* x, const int8_t* e, int d) 
     return v;
 }
 
-__device__ __forceinline__ double dmono_at0(const int8_t* e, int d, int axis) {
-    int deg = 0;
-    for (int k = 0; k < d; ++k) deg += e[k];
-    return (deg == 1 && e[axis] == 1) ? 1.0 : 0.0;
+// u . grad p at 0 for the monomial with exponents e: u_k for p = x_k, else 0
+__device__ __forceinline__ double dmono_at0(const int8_t* e, int d, const double* u) {
+    int deg = 0, ax = 0;
+    for (int k = 0; k < d; ++k) {
+        deg += e[k];
+        if (e[k] == 1) ax = k;
+    }
+    return deg == 1 ? u[ax] : 0.0;
 }
 
 __global__ __launch_bounds__(1024) void k_weights(WArgs a) {
@@ -363,23 +368,29 @@ __global__ __launch_bounds__(1024) void k_weights(WArgs a) {
                 v = mono(xi + j * 3, a.ex[i - n], d);
             }
         } else {
-            const int col = j - R;   // right-hand side index (axis for derivatives)
+            const int col = j - R;   // right-hand side index (derivative direction)
+            const double* u = a.fu[col];
             if (a.kind == W_FD) {
                 if (i < n) {
-                    double r2 = 0.0;
-                    for (int k = 0; k < d; ++k) r2 += xi[i * 3 + k] * xi[i * 3 + k];
+                    double r2 = 0.0, xu = 0.0;
+                    for (int k = 0; k < d; ++k) {
+                        r2 += xi[i * 3 + k] * xi[i * 3 + k];
+                        xu += xi[i * 3 + k] * u[k];
+                    }
                     const double r = sqrt(r2);
-                    // d/dx_col |x - xi_i|^k at x = 0 = -k r^(k-2) xi_{i,col}
-                    v = -(double)a.phs_k * phs(r, a.phs_k - 2) * xi[i * 3 + col];
+                    // u . grad |x - xi_i|^k at x = 0 = -k r^(k-2) (xi_i . u)
+                    v = -(double)a.phs_k * phs(r, a.phs_k - 2) * xu;
                 } else {
-                    v = dmono_at0(a.ex[i - n], d, col);
+                    v = dmono_at0(a.ex[i - n], d, u);
                 }
             } else if (a.kind == W_VFD) {
-                // central virtual difference: (-1/2 f(-delta e) + 1/2 f(+delta e)) / delta
+                // central virtual difference: (-1/2 f(-delta u) + 1/2 f(+delta u)) / delta
                 const double dl = a.vdelta / sc;
                 double xm[3] = {0, 0, 0}, xp[3] = {0, 0, 0};
-                xm[col] = -dl;
-                xp[col] = dl;
+                for (int k = 0; k < d; ++k) {
+                    xm[k] = -dl * u[k];
+                    xp[k] = dl * u[k];
+                }
                 double fm, fp;
                 if (i < n) {
                     double r2m = 0.0, r2p = 0.0;
@@ -1049,6 +1060,15 @@ static int launch_weights(rbffd_plan* p, const OpBlock& o, const NodeSet& T, con
         a.nrhs = d;
         a.upow = 1;
         a.vdelta = p->p.vfd_sigma * p->p.h;
+        for (int q = 0; q < 3; ++q)
+            for (int k = 0; k < 3; ++k) a.fu[q][k] = (q == k) ? 1.0 : 0.0;
+        if (p->p.frame_angle != 0.0) {
+            const double cs = std::cos(p->p.frame_angle), sn = std::sin(p->p.frame_angle);
+            a.fu[0][0] = cs;
+            a.fu[0][1] = sn;
+            a.fu[1][0] = -sn;
+            a.fu[1][1] = cs;
+        }
         for (int q = 0; q < p->M; ++q)
             for (int k = 0; k < 3; ++k) a.ex[q][k] = (int8_t)p->ex_m[q][k];
         a.out = o.wc;

@@ -53,7 +53,8 @@ class Solver:
 
     def __init__(self, dim, xyz, flags, h, n, m, alpha, hv_c, lo, hi, *, n_hv=0, dt=0.0, mode="FD",
                  bc="PEC", eps0=1.0, mu0=1.0, vfd_sigma=0.5, phs_k=3, precision="f64", K=1,
-                 adjoint=False, reorder="MORTON", xyz_h=None, flags_h=None, h_h=0.0, pol="TM", device="cuda:0"):
+                 adjoint=False, reorder="MORTON", xyz_h=None, flags_h=None, h_h=0.0, pol="TM", frame_angle=0.0,
+                 device="cuda:0"):
         self.lib = _abi.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the rbffd library needs a GPU (no CPU path)")
@@ -68,6 +69,7 @@ class Solver:
         p.fdtype = _abi.DTYPE[precision]
         p.K, p.adjoint = K, int(bool(adjoint))
         p.pol = {"TM": 0, "TE": 1}[pol]
+        p.frame_angle = frame_angle
         p.vfd_sigma, p.hv_c, p.h, p.h_h, p.dt, p.eps0, p.mu0 = vfd_sigma, hv_c, h, h_h, dt, eps0, mu0
         for k in range(dim):
             p.lo[k], p.hi[k] = lo[k], hi[k]
@@ -113,7 +115,7 @@ class Solver:
     def from_workload(cls, w, precision="f64", **kw):
         args = dict(n_hv=w.n_hv, mode=w.mode, bc=w.bc, eps0=w.eps0, mu0=w.mu0, vfd_sigma=w.vfd_sigma,
                     precision=precision, xyz_h=w.xyz_h, flags_h=w.flags_h, h_h=w.h_h or 0.0,
-                    pol=getattr(w, "pol", "TM"))
+                    pol=getattr(w, "pol", "TM"), frame_angle=getattr(w, "frame_angle", 0.0))
         args.update(kw)
         return cls(w.dim, w.xyz, w.flags, w.h, w.n, w.m, w.alpha, w.hv_c, w.lo, w.hi, **args)
 

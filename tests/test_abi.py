@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 def test_struct_layouts_match_header_sizes():
     _abi, _ = _lib()
     # params: 14 int32 + 7 doubles + 6 doubles
-    assert C.sizeof(_abi.Params) == 14 * 4 + 13 * 8
+    assert C.sizeof(_abi.Params) == 14 * 4 + 14 * 8
     assert C.sizeof(_abi.Fields) == 5 * 8 + 8
     # run args: 8 int32, 7 pointers, 1 double
     assert C.sizeof(_abi.RunArgs) == 8 * 4 + 7 * 8 + 8
@@ -92,8 +92,21 @@ def test_plan_validation_and_sizes_on_host():
     assert s.fe == 2 and s.fh == 1 and s.e_bytes == 121 * 2 * 8 and s.h_bytes == 121 * 8
     lib.rbffd_plan_destroy(plan)
     for bad, code in ((dict(pol=2), _abi.EINVAL), (dict(pol=1, K=4, fdtype=1, wdtype=1), _abi.ENOTSUP),
-                      (dict(pol=1, adjoint=1), _abi.ENOTSUP), (dict(pol=1, mode=2), _abi.ENOTSUP)):
+                      (dict(pol=1, adjoint=1), _abi.ENOTSUP), (dict(pol=1, mode=2), _abi.ENOTSUP),
+                      # rotated frame: 2D only, finite, not with axis-aligned TEz walls
+                      (dict(frame_angle=float("nan")), _abi.EINVAL),
+                      (dict(pol=1, frame_angle=0.3), _abi.ENOTSUP)):
         p = _params(_abi, **bad)
         rc = lib.rbffd_plan_create(C.byref(p), xyz.shape[0], xyz.ctypes.data, flags.ctypes.data, 0, None, None,
                                    C.byref(plan))
         assert rc == code, bad
+    nowall = np.zeros_like(flags)
+    for good in (dict(frame_angle=0.3, mode=1), dict(frame_angle=-0.7, pol=1, bc=1)):
+        p = _params(_abi, **good)
+        fl = nowall if good.get("bc") == 1 else flags
+        if good.get("bc") == 1:
+            p.hi[0] = p.hi[1] = 1.1                  # nodes in [lo, hi)
+        rc = lib.rbffd_plan_create(C.byref(p), xyz.shape[0], xyz.ctypes.data, fl.ctypes.data, 0, None, None,
+                                   C.byref(plan))
+        assert rc == 0, (good, lib.rbffd_strerror(rc))
+        lib.rbffd_plan_destroy(plan)

@@ -8,7 +8,13 @@
   measure of eq. 26 falls from n = 20 to n = 60 with RBF-FD and reaches the
   quantisation floor of exact advection; RBF-VFD is the more dispersive at
   n = 60 (the observations around Figures 8-10); the energy stays bounded.
+* Angle study (eq. 27, Figures 11-12; the curl in a frame turned by -phi):
+  GPU weights in the turned frame against the oracle's (FP64 1e-9), line
+  traces at phi = pi/6 against the oracle, and at full size RBF-FD gives the
+  same traces for every phi while RBF-VFD does not.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -18,7 +24,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_2508_18205_amd import Solver  # noqa: E402
+from paper_2508_18205_amd import Solver, _abi  # noqa: E402
 from oracle import dispersion as D, setup as osetup  # noqa: E402
 from synth import configs  # noqa: E402
 
@@ -27,10 +33,11 @@ def _announce(msg):
     print(msg, flush=True)
 
 
-@pytest.mark.parametrize("mode,n", [("FD", 13), ("FD", 30), ("VFD", 13), ("VFD", 30)])
-def test_line_traces_match_oracle(mode, n):
-    _announce(f"dispersion parity {mode} n={n}")
-    w = configs.dispersion_2d(n=n, mode=mode, L=40.0, steps=300, chat=1e-4)
+@pytest.mark.parametrize("mode,n,phi", [("FD", 13, 0.0), ("FD", 30, 0.0), ("VFD", 13, 0.0), ("VFD", 30, 0.0),
+                                        ("FD", 13, math.pi / 6), ("VFD", 13, math.pi / 6)])
+def test_line_traces_match_oracle(mode, n, phi):
+    _announce(f"dispersion parity {mode} n={n} phi={phi:.4f}")
+    w = configs.dispersion_2d(n=n, mode=mode, L=40.0, steps=300, chat=1e-4, phi=phi)
     oh, oe = osetup.operators(w)
     _, _, _, tr_o = osetup.run_workload(w, oh, oe)
     scale = np.abs(tr_o).max()
@@ -72,4 +79,47 @@ def test_dispersion_falls_with_stencil_size_full_size():
     assert fd60 <= floor * (1 + 1e-9)
     assert vfd60 > 2 * fd60
     for u in (u20, u60, uv60):
+        assert np.isfinite(u).all() and 0.9 < u.min() and u.max() < 1.1
+
+
+@pytest.mark.parametrize("mode", ["FD", "VFD"])
+def test_turned_frame_weights_match_oracle(mode):
+    _announce(f"turned-frame weights {mode}")
+    for phi in (math.pi / 6, math.pi / 4, -1.1):
+        w = configs.dispersion_2d(n=30, mode=mode, L=40.0, steps=10, phi=phi)
+        s = Solver.from_workload(w, precision="f64")
+        oh, _ = osetup.operators(w)
+        g = s.weights(_abi.OP_CURL_H)
+        o = oh["curl_w"][s.perm]
+        err = (np.abs(g - o).reshape(g.shape[0], -1).max(axis=1) / np.abs(o).reshape(o.shape[0], -1).max(axis=1))
+        _announce(f"  phi={phi:.4f}: max rel weight err {err.max():.2e}")
+        assert err.max() < 1e-9
+
+
+def _line(mode, phi, n=60):
+    w = configs.dispersion_2d(n=n, mode=mode, phi=phi)
+    s = Solver.from_workload(w, precision="f32")
+    st = s.state(w.E0, w.H0)
+    r = s.run(st, w.steps, energy_every=20, rcv=w.rcv_node, use_graph=True)
+    tr = r["traces"].double().cpu().numpy()
+    return tr, D.line_samples(tr, w.meta["save_every"]), r["energy"] / r["energy"][0]
+
+
+def test_angle_study_full_size():
+    fd0, s_fd0, _ = _line("FD", 0.0)
+    fd45, s_fd45, u_fd = _line("FD", math.pi / 4)
+    vfd0, s_v0, _ = _line("VFD", 0.0)
+    vfd45, s_v45, u_v = _line("VFD", math.pi / 4)
+    scale = np.abs(fd0).max()
+    d_fd = np.abs(fd45 - fd0).max() / scale
+    d_vfd = np.abs(vfd45 - vfd0).max() / scale
+    e = [D.err_l1(x, 15)[0] for x in (s_fd0, s_fd45, s_v0, s_v45)]
+    _announce(f"  traces phi=pi/4 vs 0: FD {d_fd:.2e} VFD {d_vfd:.2e}; ||err||_1 FD {e[0]:.4f} {e[1]:.4f} "
+              f"VFD {e[2]:.4f} {e[3]:.4f}")
+    # RBF-FD: the same scheme in every frame (FP32 rounding only)
+    assert d_fd < 1e-4
+    assert abs(e[1] - e[0]) <= 1e-6 + 1e-3 * e[0]
+    # RBF-VFD: the virtual points do not turn with the frame
+    assert d_vfd > 100 * d_fd
+    for u in (u_fd, u_v):
         assert np.isfinite(u).all() and 0.9 < u.min() and u.max() < 1.1
