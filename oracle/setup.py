@@ -54,8 +54,9 @@ def run_workload(w, op_h, op_e, steps=None, energy_every=0, use_eps=True, src=Tr
     gamma = _step.hv_gamma(w.hv_c, w.alpha, w.h) if w.alpha > 0 else 0.0
     if getattr(w, "pol", "TM") == "TE":
         keep = _step.pec_keep_te(w.flags) if w.bc == "PEC" else np.ones((w.N, 2))
+        nrm = w.normals if w.bc == "PEC" else None
         E, Hz, en = _step.run_te(w.E0, w.H0, op_h, w.dt, steps, gamma, w.dt / w.eps0, keep, mu0=w.mu0,
-                                 eps0=w.eps0, h=w.h, energy_every=energy_every)
+                                 eps0=w.eps0, h=w.h, energy_every=energy_every, normals=nrm)
         return E, Hz, en, None
     keep = _step.pec_keep(w.flags, w.dim) if w.bc == "PEC" else np.ones((w.N, w.E0.shape[1]))
     kappa = w.dt / w.eps0

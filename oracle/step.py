@@ -122,15 +122,30 @@ def te_h_update(E, Hz, op, a, gamma, rows=None):
     return (Hc[:, 0] - a * (curl - gamma * D(hw, hi, Hz[:, 0])))[:, None]
 
 
-def te_e_update(E, Hz_new, op, kappa, gamma, keep, rows=None):
-    """E^{n+1} [N, 2] from E^n and Hz^{n+1}, then the PEC factors ``keep``."""
+def te_e_update(E, Hz_new, op, kappa, gamma, keep, rows=None, normals=None):
+    """E^{n+1} [N, 2] from E^n and Hz^{n+1}, then the PEC rule of
+    ``wall_project`` (factors ``keep``, curved-wall ``normals``)."""
     cw, ci = op["curl_w"], op["curl_idx"]
     hw, hi = op["hv_w"], op["hv_idx"]
     Ec = E if rows is None else E[rows]
     h = Hz_new[:, 0]
     Ex = Ec[:, 0] + kappa * (D(cw[:, 1], ci, h) + gamma * D(hw, hi, E[:, 0]))
     Ey = Ec[:, 1] + kappa * (-D(cw[:, 0], ci, h) + gamma * D(hw, hi, E[:, 1]))
-    return np.stack([Ex, Ey], axis=1) * keep
+    return wall_project(np.stack([Ex, Ey], axis=1), keep, normals)
+
+
+def wall_project(E, keep, normals=None):
+    """PEC on in-plane E [N, 2]: the tangential part vanishes on the wall.
+
+    Component c survives where keep[:, c] = 1 (walls normal to an axis); at a
+    node with a unit normal n (a curved wall) only the normal component
+    survives, E <- (E . n) n.  ``normals`` [N, 2] is zero off the wall."""
+    out = E * keep
+    if normals is not None:
+        sel = np.abs(normals).sum(axis=1) > 0
+        en = (E[sel] * normals[sel]).sum(axis=1)
+        out[sel] = en[:, None] * normals[sel]
+    return out
 
 
 def pec_keep_te(flags):
@@ -142,7 +157,8 @@ def pec_keep_te(flags):
     return keep
 
 
-def run_te(E, Hz, op, dt, steps, gamma, kappa, keep, mu0=1.0, eps0=1.0, h=None, energy_every=0):
+def run_te(E, Hz, op, dt, steps, gamma, kappa, keep, mu0=1.0, eps0=1.0, h=None, energy_every=0,
+           normals=None):
     """TEz counterpart of ``run``: returns (E, Hz, energies)."""
     a = dt / mu0
     eta0 = math.sqrt(mu0 / eps0)
@@ -153,7 +169,7 @@ def run_te(E, Hz, op, dt, steps, gamma, kappa, keep, mu0=1.0, eps0=1.0, h=None, 
         Hn = te_h_update(E, Hz, op, a, gamma)
         if energy_every and n % energy_every == 0:
             energies.append(energy(E, Hz, Hn, h, h, eta0, 2))
-        E = te_e_update(E, Hn, op, kappa, gamma, keep)
+        E = te_e_update(E, Hn, op, kappa, gamma, keep, normals=normals)
         Hz = Hn
     return E, Hz, np.array(energies)
 

@@ -70,6 +70,7 @@ class Workload:
     # extras
     pol: str = "TM"           # 2D polarisation: TM (Ez, Hx, Hy) | TE (Ex, Ey, Hz)
     frame_angle: float = 0.0  # 2D: angle of the frame the curl is discretised in
+    normals: Optional[np.ndarray] = None       # [N, 2] unit wall normals (curved TEz walls), 0 elsewhere
     K: int = 1
     E0_batch: Optional[np.ndarray] = None      # [K, N, FE]
     eps_r: Optional[np.ndarray] = None
@@ -248,6 +249,24 @@ def tm01_disk(h=0.02, R=1.0, n=12, m=2, alpha=2, chat=1e-3, periods=1.0, seed=9)
     return w
 
 
+def te01_disk(h=0.02, R=1.0, n=12, m=2, alpha=2, chat=1e-3, periods=1.0, seed=9):
+    """Circular PEC cavity in the TEz polarisation with its TE_01 mode for
+    ``periods`` periods; the same nodes as ``tm01_disk``, with the outward
+    unit normal of the circle on every wall node."""
+    xyz, flags, hm = _nodes.disk_nodes(R, h, seed=seed)
+    w = Workload("te01_disk", 2, xyz, flags, h, n, m, alpha, _hv_default(2, alpha), chat, 0,
+                 lo=(-R, -R), hi=(R, R), pol="TE")
+    wall = flags != 0
+    nrm = np.zeros((w.N, 2))
+    nrm[wall] = xyz[wall] / np.hypot(xyz[wall, 0], xyz[wall, 1])[:, None]
+    w.normals = nrm
+    E0, H0, om = _fields.te01_disk(xyz, 0.0, -0.5 * w.dt, R=R)
+    w.E0, w.H0 = E0, H0
+    w.steps = int(round(periods * 2 * math.pi / om / w.dt))
+    w.meta.update(R=R, omega=om, h_mean=hm)
+    return w
+
+
 REGISTRY = {
     "tm_cavity_2d": tm_cavity_2d,
     "pulse_2d": pulse_2d,
@@ -258,6 +277,7 @@ REGISTRY = {
     "dispersion_2d": dispersion_2d,
     "tm01_disk": tm01_disk,
     "te_cavity_2d": te_cavity_2d,
+    "te01_disk": te01_disk,
 }
 
 

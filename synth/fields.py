@@ -111,6 +111,30 @@ def periodic_plane_pulse(xyz, t_e, t_h, L=200.0, sigma=30.0, phi=0.0, eps0=1.0,
     return E, H
 
 
+def te01_disk(xyz, t_e, t_h, R=1.0, centre=(0.0, 0.0), eps0=1.0, mu0=1.0):
+    """TE_01 mode of the circular PEC cavity of radius R (2D TEz).
+
+    Hz = J0(k r) cos(omega t), k = j_11 / R (first zero of J1, where the
+    tangential E vanishes), omega = c0 k; Ampere's law gives
+    E = eta0 J1(k r) (-sin theta, cos theta) sin(omega t).  Returns
+    (E [N, 2] at t_e, Hz [N, 1] at t_h, omega).
+    """
+    from scipy import special
+    c0, eta0 = consts(eps0, mu0)
+    k = special.jn_zeros(1, 1)[0] / R
+    om = c0 * k
+    dx = xyz[:, 0] - centre[0]
+    dy = xyz[:, 1] - centre[1]
+    r = np.hypot(dx, dy)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        st = np.where(r > 0, dy / np.where(r > 0, r, 1.0), 0.0)
+        ct = np.where(r > 0, dx / np.where(r > 0, r, 1.0), 0.0)
+    amp = eta0 * special.j1(k * r) * math.sin(om * t_e)
+    E = np.stack([-amp * st, amp * ct], axis=1)
+    Hz = (special.j0(k * r) * math.cos(om * t_h))[:, None]
+    return E, Hz, om
+
+
 def in_frame(H, theta):
     """Components of the 2D vectors H [N, 2] in the frame with axes
     u_1 = (cos theta, sin theta), u_2 = (-sin theta, cos theta)."""

@@ -282,3 +282,40 @@ def test_te11_cavity_converges():
     assert e2 < 3e-4 and m2 < 3e-4
     assert math.log(e1 / e2) / math.log(h1 / h2) >= 1.5
     assert math.log(m1 / m2) / math.log(h1 / h2) >= 1.5
+
+
+def test_te01_circular_cavity_converges():
+    # a curved PEC wall in the TEz polarisation: only the normal component of
+    # (Ex, Ey) survives on the wall nodes.  The TE_01 mode (Hz = J0(j11 r / R)
+    # cos(omega t), E azimuthal, closed form) after 1 1/8 periods (E is not
+    # near a zero of sin(omega t) there)
+    res = []
+    for h in (0.05, 0.025):
+        w = configs.te01_disk(h=h, periods=1.125)
+        oh, oe = setup.operators(w)
+        E, Hz, _, _ = setup.run_workload(w, oh, oe)
+        Ea, Ha, _ = fields.te01_disk(w.xyz, w.steps * w.dt, (w.steps - 0.5) * w.dt)
+        wall = w.flags > 0
+        # tangential E vanishes on the wall (to rounding)
+        tang = -E[wall, 0] * w.normals[wall, 1] + E[wall, 1] * w.normals[wall, 0]
+        assert np.abs(tang).max() < 1e-15
+        res.append(step.linf_errors(E, Hz, Ea, Ha) + (w.meta["h_mean"],))
+    (eE1, eH1, h1), (eE2, eH2, h2) = res
+    assert eE1 < 3e-3 and eH1 < 3e-3
+    assert math.log(eE1 / eE2) / math.log(h1 / h2) >= 1.5
+    assert math.log(eH1 / eH2) / math.log(h1 / h2) >= 1.5
+
+
+def test_wall_projection_on_axis_normals_is_the_axis_rule():
+    # a unit normal along an axis keeps exactly the component the axis rule keeps
+    rs = np.random.default_rng(3)
+    E = rs.standard_normal((6, 2))
+    flags = np.array([1, 2, 4, 8, 0, 0], dtype=np.uint8)
+    nrm = np.array([[-1.0, 0], [1.0, 0], [0, -1.0], [0, 1.0], [0, 0], [0, 0]])
+    keep = step.pec_keep_te(flags)
+    assert np.array_equal(step.wall_project(E, keep, nrm), step.wall_project(E, keep))
+    # a diagonal normal keeps the normal part only
+    n = np.array([[0.6, 0.8]])
+    out = step.wall_project(E[:1], np.ones((1, 2)), n)
+    assert abs(out[0, 0] * 0.8 - out[0, 1] * 0.6) < 1e-15
+    assert abs((out[0] * n[0]).sum() - (E[0] * n[0]).sum()) < 1e-15
