@@ -566,29 +566,32 @@ def main():
         extras["dispersion"] = disp
         log(f"dispersion: {disp}")
     if "disk" in legs:
-        # curved PEC wall: circular cavity with ~0.5M nodes, TM_01 mode, one
-        # period, FP32; error against the Bessel solution
+        # curved PEC wall: circular cavity with ~0.5M nodes, one period, FP32,
+        # error against the Bessel solution: TM_01 (TMz) and TE_01 (TEz, wall
+        # nodes keep the normal component of E)
         from synth import fields as _fields
-        wk = configs.tm01_disk(h=0.0025)
-        sk, tk = setup_w(wk, "f32")
-        ak = sk.state(wk.E0, wk.H0)
-        if not args.no_tune:
-            sk.autotune(ak, reps=5)
+        for key, make, exact in (("tm01_disk", configs.tm01_disk, _fields.tm01_disk),
+                                 ("te01_disk", configs.te01_disk, _fields.te01_disk)):
+            wk = make(h=0.0025)
+            sk, tk = setup_w(wk, "f32")
             ak = sk.state(wk.E0, wk.H0)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        sk.run(ak, wk.steps, use_graph=True)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        tk2 = e0.elapsed_time(e1) * 1e-3
-        Ea, Ha, _ = _fields.tm01_disk(wk.xyz, wk.steps * wk.dt, (wk.steps - 0.5) * wk.dt)
-        Ek, Hk = sk.E_original(ak), sk.H_original(ak)
-        extras["tm01_disk"] = {"N": wk.N, "steps": wk.steps, "node_steps_per_s": wk.N * wk.steps / tk2,
-                               "linf_E_vs_bessel": float(np.abs(Ek - Ea).max()),
-                               "linf_H_vs_bessel": float(np.abs(Hk - Ha).max()), "setup_s": round(tk, 2)}
-        log(f"disk: {extras['tm01_disk']}")
-        del sk, ak
-        torch.cuda.empty_cache()
+            if not args.no_tune:
+                sk.autotune(ak, reps=5)
+                ak = sk.state(wk.E0, wk.H0)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            sk.run(ak, wk.steps, use_graph=True)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tk2 = e0.elapsed_time(e1) * 1e-3
+            Ea, Ha, _ = exact(wk.xyz, wk.steps * wk.dt, (wk.steps - 0.5) * wk.dt)
+            Ek, Hk = sk.E_original(ak), sk.H_original(ak)
+            extras[key] = {"N": wk.N, "steps": wk.steps, "node_steps_per_s": wk.N * wk.steps / tk2,
+                           "linf_E_vs_bessel": float(np.abs(Ek - Ea).max()),
+                           "linf_H_vs_bessel": float(np.abs(Hk - Ha).max()), "setup_s": round(tk, 2)}
+            log(f"disk: {key} {extras[key]}")
+            del sk, ak
+            torch.cuda.empty_cache()
     if "te" in legs:
         # TEz polarisation: TE_11 mode of the PEC square on a 1001^2 jittered
         # grid (1.0M nodes, n = 12, n_hv = 31), one period, FP32

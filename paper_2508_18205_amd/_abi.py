@@ -74,6 +74,7 @@ PROTOTYPES = {
     "rbffd_plan_create": (C.c_int, [C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                                     C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "rbffd_plan_sizes": (C.c_int, [C.c_void_p, C.POINTER(Sizes)]),
+    "rbffd_set_wall_normals": (C.c_int, [C.c_void_p, C.c_void_p]),
     "rbffd_plan_destroy": (None, [C.c_void_p]),
     "rbffd_strerror": (C.c_char_p, [C.c_int]),
     "rbffd_last_error": (C.c_char_p, [C.c_void_p]),

@@ -80,7 +80,11 @@ struct NodeSet {
     int32_t* perm = nullptr;      // internal -> original
     int32_t* inv = nullptr;       // original -> internal
     double* xyz = nullptr;        // [N][dim] internal order
-    uint8_t* emask = nullptr;     // [N] bit c = E component c free (E set only)
+    uint8_t* emask = nullptr;     // [N] bit c = E component c free (E set only);
+                                  // bit 3 = curved wall with a normal in nrm
+    std::vector<double> nrm_host; // [N][2] unit wall normals, original order (TEz)
+    double* nrm_in = nullptr;     // [N][2] original order (TEz PEC plans only)
+    double* nrm = nullptr;        // [N][2] internal order
     double h = 0;
 };
 

@@ -209,7 +209,8 @@ __global__ void k_relabel(const int32_t* knn_orig, int k, const int32_t* tperm, 
 }
 
 __global__ void k_internal_nodes(const double* xyz_in, const uint8_t* flags_in, const int32_t* perm, int64_t N, int d,
-                                 double* xyz, uint8_t* emask, int periodic, int te) {
+                                 double* xyz, uint8_t* emask, int periodic, int te, const double* nrm_in,
+                                 double* nrm) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int64_t o = perm[p];
@@ -223,6 +224,12 @@ __global__ void k_internal_nodes(const double* xyz_in, const uint8_t* flags_in, 
         keep = 3;                           // (Ex, Ey): only the normal component survives
         for (int k = 0; k < 2; ++k)
             if (f & (3u << (2 * k))) keep &= (uint8_t)(1u << k);
+        if (nrm) {                          // curved wall: project on the given normal
+            const double nx = nrm_in[2 * o], ny = nrm_in[2 * o + 1];
+            nrm[2 * p] = nx;
+            nrm[2 * p + 1] = ny;
+            if (nx != 0.0 || ny != 0.0) keep |= 8;
+        }
     } else {
         keep = 7;
         for (int k = 0; k < 3; ++k)
@@ -978,6 +985,10 @@ int setup_nodes_and_stencils(rbffd_plan* p, void* wsp, hipStream_t st) {
     // upload node data
     HIPCHK(p, hipMemcpyAsync(p->E.xyz_in, p->E.xyz_host.data(), p->E.N * d * 8, hipMemcpyHostToDevice, st));
     HIPCHK(p, hipMemcpyAsync(p->E.flags_in, p->E.flags_host.data(), p->E.N, hipMemcpyHostToDevice, st));
+    if (p->E.nrm_in) {
+        if (p->E.nrm_host.empty()) HIPCHK(p, hipMemsetAsync(p->E.nrm_in, 0, p->E.N * 16, st));
+        else HIPCHK(p, hipMemcpyAsync(p->E.nrm_in, p->E.nrm_host.data(), p->E.N * 16, hipMemcpyHostToDevice, st));
+    }
     int rc = build_search(p, p->E, se, st);
     if (rc) return rc;
     if (!p->collocated) {
@@ -1012,7 +1023,7 @@ int setup_nodes_and_stencils(rbffd_plan* p, void* wsp, hipStream_t st) {
         }
         hipLaunchKernelGGL(k_inverse, dim3(blocks(S.N)), dim3(256), 0, st, S.perm, S.N, S.inv);
         hipLaunchKernelGGL(k_internal_nodes, dim3(blocks(S.N)), dim3(256), 0, st, S.xyz_in, S.flags_in, S.perm, S.N, d,
-                           S.xyz, S.emask, (int)per, (int)(p->p.pol == RBFFD_POL_TE));
+                           S.xyz, S.emask, (int)per, (int)(p->p.pol == RBFFD_POL_TE), S.nrm_in, S.nrm);
         return RBFFD_OK;
     };
     if (p->p.reorder == RBFFD_ORDER_RCM && !p->collocated)

@@ -43,6 +43,7 @@ struct SA {
     double dt, eps0;
     const void* eps_r;    // per-node eps_r (double for FP64 fields, else float) or null
     const uint8_t* emask;
+    const double* wnrm;   // [N][2] unit wall normals (TEz curved walls; emask bit 3)
     // TEz: the 2D kernels with the fields' roles exchanged.  te = 1: the
     // vector kernel updates (Ex, Ey) from Hz with factor -kappa_i and the wall
     // mask; nomask = 1: the scalar kernel updates Hz (no wall mask)
@@ -53,6 +54,22 @@ struct SA {
     const int32_t* hoff;
     int Q8, hmax;
 };
+
+// PEC on the in-plane E of the TEz polarisation: bit 0 / 1 of the mask keeps
+// Ex / Ey (walls normal to an axis); bit 3 marks a curved-wall node with unit
+// normal n = wn[i], where only the normal component survives: E <- (E . n) n
+template <typename TC>
+__device__ __forceinline__ void te_wall(uint8_t m, const double* wn, int64_t i, TC& x, TC& y) {
+    if (m & 8) {
+        const TC nx = (TC)wn[2 * i], ny = (TC)wn[2 * i + 1];
+        const TC en = x * nx + y * ny;
+        x = en * nx;
+        y = en * ny;
+    } else {
+        x = (m & 1) ? x : (TC)0;
+        y = (m & 2) ? y : (TC)0;
+    }
+}
 
 template <typename TS, typename TW>
 __device__ __forceinline__ int64_t tile_of(const SA<TS, TW>& a) {
@@ -140,8 +157,9 @@ __global__ __launch_bounds__(512) void k_h2(SA<TS, TW> a) {
             // written as E - kappa (-D^dy Hz - gamma HV, D^dx Hz - gamma HV) with
             // the host's gamma negated; then the wall mask
             const TC A = -kappa_of(a, i);
-            const uint8_t m = a.emask[i];
-            S::st2(a.out, i, (m & 1) ? hx0 + A * (-dy + G * vx) : (TC)0, (m & 2) ? hy0 + A * (dx + G * vy) : (TC)0);
+            TC ex = hx0 + A * (-dy + G * vx), ey = hy0 + A * (dx + G * vy);
+            te_wall(a.emask[i], a.wnrm, i, ex, ey);
+            S::st2(a.out, i, ex, ey);
         }
     }
 }
@@ -259,8 +277,9 @@ __global__ __launch_bounds__(512) void k_h2x(SA<TS, TW> a) {
             // written as E - kappa (-D^dy Hz - gamma HV, D^dx Hz - gamma HV) with
             // the host's gamma negated; then the wall mask
             const TC A = -kappa_of(a, i);
-            const uint8_t m = a.emask[i];
-            S::st2(a.out, i, (m & 1) ? hx0 + A * (-dy + G * vx) : (TC)0, (m & 2) ? hy0 + A * (dx + G * vy) : (TC)0);
+            TC ex = hx0 + A * (-dy + G * vx), ey = hy0 + A * (dx + G * vy);
+            te_wall(a.emask[i], a.wnrm, i, ex, ey);
+            S::st2(a.out, i, ex, ey);
         }
     }
 }
@@ -375,8 +394,9 @@ __global__ __launch_bounds__(256) void k_h2s(SA<TS, TW> a) {
         S::st2(a.out, i, hx0 + A * (-dy + G * vx), hy0 + A * (dx + G * vy));
     } else {
         const TC A = -kappa_of(a, i);
-        const uint8_t m = a.emask[i];
-        S::st2(a.out, i, (m & 1) ? hx0 + A * (-dy + G * vx) : (TC)0, (m & 2) ? hy0 + A * (dx + G * vy) : (TC)0);
+        TC ex = hx0 + A * (-dy + G * vx), ey = hy0 + A * (dx + G * vy);
+        te_wall(a.emask[i], a.wnrm, i, ex, ey);
+        S::st2(a.out, i, ex, ey);
     }
 }
 
@@ -795,8 +815,9 @@ __global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
             // written as E - kappa (-D^dy Hz - gamma HV, D^dx Hz - gamma HV) with
             // the host's gamma negated; then the wall mask
             const TC A = -kappa_of(a, i);
-            const uint8_t m = a.emask[i];
-            S::st2(a.out, i, (m & 1) ? hx0 + A * (-dy + G * vx) : (TC)0, (m & 2) ? hy0 + A * (dx + G * vy) : (TC)0);
+            TC ex = hx0 + A * (-dy + G * vx), ey = hy0 + A * (dx + G * vy);
+            te_wall(a.emask[i], a.wnrm, i, ex, ey);
+            S::st2(a.out, i, ex, ey);
         }
     }
 }
@@ -1351,6 +1372,7 @@ void fill_sa(const rbffd_plan* p, const OpBlock& o, SA<TS, TW>& a, bool hupd) {
     a.eps0 = p->p.eps0;
     a.a = hupd ? p->dt / p->p.mu0 : p->dt / p->p.eps0;
     a.emask = p->E.emask;
+    a.wnrm = p->E.nrm;
     a.lidx = (const uint4*)o.lidx;
     a.hpool = o.hpool;
     a.hoff = o.hoff;

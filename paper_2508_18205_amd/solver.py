@@ -54,7 +54,7 @@ class Solver:
     def __init__(self, dim, xyz, flags, h, n, m, alpha, hv_c, lo, hi, *, n_hv=0, dt=0.0, mode="FD",
                  bc="PEC", eps0=1.0, mu0=1.0, vfd_sigma=0.5, phs_k=3, precision="f64", K=1,
                  adjoint=False, reorder="MORTON", xyz_h=None, flags_h=None, h_h=0.0, pol="TM", frame_angle=0.0,
-                 device="cuda:0"):
+                 normals=None, device="cuda:0"):
         self.lib = _abi.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the rbffd library needs a GPU (no CPU path)")
@@ -92,6 +92,10 @@ class Solver:
                                         fh.ctypes.data if fh is not None else None, C.byref(plan))
         check(rc, None, "rbffd_plan_create")
         self.plan = plan
+        if normals is not None:
+            nrm = np.ascontiguousarray(normals, dtype=np.float64)
+            assert nrm.shape == (self.xyz.shape[0], 2)
+            check(self.lib.rbffd_set_wall_normals(plan, nrm.ctypes.data), plan, "set_wall_normals")
         s = _abi.Sizes()
         check(self.lib.rbffd_plan_sizes(plan, C.byref(s)), plan, "plan_sizes")
         self.sizes = s
@@ -115,7 +119,8 @@ class Solver:
     def from_workload(cls, w, precision="f64", **kw):
         args = dict(n_hv=w.n_hv, mode=w.mode, bc=w.bc, eps0=w.eps0, mu0=w.mu0, vfd_sigma=w.vfd_sigma,
                     precision=precision, xyz_h=w.xyz_h, flags_h=w.flags_h, h_h=w.h_h or 0.0,
-                    pol=getattr(w, "pol", "TM"), frame_angle=getattr(w, "frame_angle", 0.0))
+                    pol=getattr(w, "pol", "TM"), frame_angle=getattr(w, "frame_angle", 0.0),
+                    normals=getattr(w, "normals", None) if w.bc == "PEC" else None)
         args.update(kw)
         return cls(w.dim, w.xyz, w.flags, w.h, w.n, w.m, w.alpha, w.hv_c, w.lo, w.hi, **args)
 

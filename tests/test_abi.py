@@ -110,3 +110,36 @@ def test_plan_validation_and_sizes_on_host():
                                    C.byref(plan))
         assert rc == 0, (good, lib.rbffd_strerror(rc))
         lib.rbffd_plan_destroy(plan)
+
+
+def test_wall_normals_validation_on_host():
+    _abi, lib = _lib()
+    from synth import nodes
+    xyz, flags, h = nodes.jittered_grid((11, 11), seed=1)
+    xyz = np.ascontiguousarray(xyz)
+    N = xyz.shape[0]
+    plan = C.c_void_p()
+
+    def make(**kw):
+        p = _params(_abi, **kw)
+        assert lib.rbffd_plan_create(C.byref(p), N, xyz.ctypes.data, flags.ctypes.data, 0, None, None,
+                                     C.byref(plan)) == 0
+        return plan
+
+    nrm = np.zeros((N, 2))
+    wall = np.nonzero(flags)[0]
+    nrm[wall, 0] = 1.0
+    pl = make()                                              # TMz: Ez needs no normal
+    assert lib.rbffd_set_wall_normals(pl, nrm.ctypes.data) == _abi.ENOTSUP
+    lib.rbffd_plan_destroy(pl)
+    pl = make(pol=1)
+    assert lib.rbffd_set_wall_normals(pl, nrm.ctypes.data) == 0
+    assert lib.rbffd_set_wall_normals(pl, None) == 0
+    bad = nrm.copy()
+    bad[wall[0]] = (0.6, 0.7)                                # not a unit vector
+    assert lib.rbffd_set_wall_normals(pl, bad.ctypes.data) == _abi.EINVAL
+    bad = nrm.copy()
+    inner = np.nonzero(flags == 0)[0][0]
+    bad[inner] = (0.0, 1.0)                                  # normal off the wall
+    assert lib.rbffd_set_wall_normals(pl, bad.ctypes.data) == _abi.EINVAL
+    lib.rbffd_plan_destroy(pl)
