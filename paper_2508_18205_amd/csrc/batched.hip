@@ -162,39 +162,44 @@ __device__ __forceinline__ int posq(const uint4& v, int half, int u) {
     return (int)((u & 1) ? (w >> 16) : (w & 0xFFFFu));
 }
 
-// The slice of every halo row (E, Hx, Hy) into LDS.  Each round a thread
-// takes SB pieces: all their list values are loaded, then all their 16-byte
-// field pieces, then the LDS stores, so that the loads are in flight together.
+// The slice of every halo row (E, Hx, Hy) into LDS.  Item it of the slice
+// is piece q = it % Q of row (k, c) = divmod(it / Q, 3), and the LDS layout
+// [k][c][KSL] puts it at it * 4 floats.  Each round a thread takes SB items:
+// all their list values are loaded, then all their 16-byte field pieces, then
+// the LDS stores, so that the loads are in flight together.
 template <int KSL>
 __device__ __forceinline__ void stage_slice(const BLA& a, float* sm, int64_t tile, int ks) {
     constexpr int SB = 8;
+    constexpr int Q = KSL / 4;            // 16-byte pieces per row slice (2 or 4)
+    constexpr int LQ = Q == 4 ? 2 : 1;
     const int h0 = a.hoff[tile], hc = a.hoff[tile + 1] - h0;
-    const int64_t K = a.K;
-    const int kof = ks * KSL;
-    constexpr int Q = KSL / 4;            // 16-byte pieces per row slice
+    const int K = a.K;
     const int items = hc * 3 * Q, nt = (int)blockDim.x, t = (int)threadIdx.x;
+    const float* E = a.E + ks * KSL;
+    const float* H = a.H + ks * KSL;
     for (int base = 0; base < items; base += SB * nt) {
         int j[SB];
 #pragma unroll
         for (int b = 0; b < SB; ++b) {
             const int it = base + b * nt + t;
-            j[b] = it < items ? a.hpool[h0 + it / (3 * Q)] : -1;
+            j[b] = it < items ? a.hpool[h0 + (int)((unsigned)(it >> LQ) / 3u)] : -1;
         }
         f4 v[SB];
 #pragma unroll
         for (int b = 0; b < SB; ++b) {
             if (j[b] < 0) continue;
             const int it = base + b * nt + t;
-            const int r = it % (3 * Q), c = r / Q, q = r - c * Q;
-            const float* src = c == 0 ? a.E + (int64_t)j[b] * K : a.H + ((int64_t)j[b] * 2 + (c - 1)) * K;
-            v[b] = ldf4(src + kof + q * 4);
+            const unsigned row = (unsigned)it >> LQ, q = (unsigned)it & (Q - 1);
+            const unsigned c = row - 3u * (row / 3u);
+            // row of the source array: E[j] or H[j][c - 1] (32-bit index, 64-bit offset)
+            const unsigned r = c == 0 ? (unsigned)j[b] : 2u * (unsigned)j[b] + c - 1u;
+            const float* src = (c == 0 ? E : H) + (uint64_t)r * (uint32_t)K + q * 4;
+            v[b] = ldf4(src);
         }
 #pragma unroll
         for (int b = 0; b < SB; ++b) {
             if (j[b] < 0) continue;
-            const int it = base + b * nt + t;
-            const int k = it / (3 * Q), r = it - k * (3 * Q), c = r / Q, q = r - c * Q;
-            stf4(sm + (k * 3 + c) * KSL + q * 4, v[b]);
+            stf4(sm + (base + b * nt + t) * 4, v[b]);
         }
     }
 }
