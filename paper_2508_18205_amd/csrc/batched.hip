@@ -169,9 +169,9 @@ __device__ __forceinline__ int posq(const uint4& v, int half, int u) {
 // the LDS stores, so that the loads are in flight together.
 template <int KSL>
 __device__ __forceinline__ void stage_slice(const BLA& a, float* sm, int64_t tile, int ks) {
-    constexpr int SB = 8;
-    constexpr int Q = KSL / 4;            // 16-byte pieces per row slice (2 or 4)
-    constexpr int LQ = Q == 4 ? 2 : 1;
+    constexpr int SB = KSL == 4 ? 4 : 8;
+    constexpr int Q = KSL / 4;            // 16-byte pieces per row slice (1, 2 or 4)
+    constexpr int LQ = Q == 4 ? 2 : (Q == 2 ? 1 : 0);
     const int h0 = a.hoff[tile], hc = a.hoff[tile + 1] - h0;
     const int K = a.K;
     const int items = hc * 3 * Q, nt = (int)blockDim.x, t = (int)threadIdx.x;
@@ -404,12 +404,16 @@ BA make_args(const rbffd_plan* p) {
 }
 
 // slice width: 16 fields (4 threads per node) when the tile's halo slice fits
-// the LDS budget and the variant asks for it, else 8 (2 threads per node)
+// the LDS budget and the variant asks for it (persist >= 16), 4 fields (one
+// thread per node, the smallest LDS footprint: more resident workgroups) for
+// persist < 8, else 8 (2 threads per node)
 int slice_tpn(const rbffd_plan* p) {
     if (!p->var.lds || p->opH.hmax <= 0) return 0;
     const int64_t per16 = (int64_t)3 * 16 * 4;
     if (p->var.persist >= 16 && p->K % 16 == 0 && p->opH.hmax * per16 <= RBFFD_LDS_BUDGET_BATCH) return 4;
+    if (p->var.persist < 8 && p->K % 4 == 0) return 1;
     if (p->K % 8 == 0) return 2;
+    if (p->K % 4 == 0) return 1;
     return 0;
 }
 
@@ -446,13 +450,15 @@ void launch_half_staged(const rbffd_plan* p, const rbffd_fields* f, int c, bool 
         a.out = (float*)f->H[o];
         a.a = (float)(p->dt / p->p.mu0);
         if (tpn == 4) hipLaunchKernelGGL(k_hbl<4>, grid, block, lds, st, a);
-        else hipLaunchKernelGGL(k_hbl<2>, grid, block, lds, st, a);
+        else if (tpn == 2) hipLaunchKernelGGL(k_hbl<2>, grid, block, lds, st, a);
+        else hipLaunchKernelGGL(k_hbl<1>, grid, block, lds, st, a);
     } else {
         a.H = (const float*)f->H[o];
         a.out = (float*)f->E[o];
         a.a = (float)(p->dt / p->p.eps0);
         if (tpn == 4) hipLaunchKernelGGL(k_ebl<4>, grid, block, lds, st, a);
-        else hipLaunchKernelGGL(k_ebl<2>, grid, block, lds, st, a);
+        else if (tpn == 2) hipLaunchKernelGGL(k_ebl<2>, grid, block, lds, st, a);
+        else hipLaunchKernelGGL(k_ebl<1>, grid, block, lds, st, a);
     }
 }
 

@@ -1698,8 +1698,8 @@ extern "C" int rbffd_autotune(rbffd_plan* p, rbffd_fields* f, int32_t reps, void
     }
     if (staged) {
         if (p->K > 1) {
-            // staged batch: 8-field slices (persist < 16) or 16-field slices
-            for (int pe : {8, 16}) cand.push_back(Variant{256, 1, pe, 1});
+            // staged batch: 4-field (persist < 8), 8-field or 16-field slices
+            for (int pe : {4, 8, 16}) cand.push_back(Variant{256, 1, pe, 1});
         } else {
             for (int x : {0, 1}) cand.push_back(Variant{256, x, 8, 1});
             // 3D with both operands fitting: also the one-operand-at-a-time kernels

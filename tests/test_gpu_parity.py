@@ -230,12 +230,13 @@ def test_run_energy_sources_receivers_graph():
     assert np.abs(T - tr).max() <= 1e-12 * np.abs(tr).max()
 
 
-@pytest.mark.parametrize("lds", [1, 0])
-def test_batched_equals_single_runs(lds):
-    _announce(f"K-field batch vs single runs (staged={lds})")
+@pytest.mark.parametrize("lds,persist", [(1, 16), (1, 8), (1, 4), (0, 8)])
+def test_batched_equals_single_runs(lds, persist):
+    # staged kernels with 16-, 8- and 4-field slices, and the global kernel
+    _announce(f"K-field batch vs single runs (staged={lds}, persist={persist})")
     w = configs.batched_2d(n_side=60, K=64, steps=100, chat=1e-3)
     sb = Solver.from_workload(w, precision="f32", K=64)
-    sb.set_variant(block=256, xcd=1, lds=lds, persist=8)
+    sb.set_variant(block=256, xcd=1, lds=lds, persist=persist)
     stb = sb.state_batched(w.E0_batch, np.zeros((64, w.N, 2)))
     sb.run(stb, w.steps, use_graph=True)
     Eb = sb.to_original(stb.E)             # [N, 1, K]
@@ -363,8 +364,8 @@ def test_batch_on_a_partial_tile():
     E0b = np.stack([fields.gaussian_pulse(xyz, (0.3 + 0.05 * k, 0.5), 0.2)[0] for k in range(8)])
     sb = Solver.from_workload(w, precision="f32", K=8)
     s1 = Solver.from_workload(w, precision="f32")
-    for lds in (1, 0):
-        sb.set_variant(block=256, xcd=1, lds=lds, persist=8)
+    for lds, pe in ((1, 8), (1, 4), (0, 8)):
+        sb.set_variant(block=256, xcd=1, lds=lds, persist=pe)
         stb = sb.state_batched(E0b, np.zeros((8, w.N, 2)))
         sb.step(stb, w.steps)
         Eb = sb.to_original(stb.E)[:, 0, :]
