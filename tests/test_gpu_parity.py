@@ -498,3 +498,33 @@ def test_te_polarisation_cavity_and_periodic():
     e = max(ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho))
     _announce(f"  periodic f64 vs oracle {e:.2e}")
     assert e < 1e-9
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_leapfrog_time_reversal_on_the_gpu(case):
+    # Without hyperviscosity the leapfrog is time reversible: T steps from
+    # (E^T, -H^{T+1}) return (E^0, -H^1).  Runs the GPU path both ways (FP64,
+    # staged and global kernels); nothing from the oracle enters.
+    from paper_2508_18205_amd.solver import State
+    _announce(f"time reversal {case}")
+    if case == "2d":
+        w = configs.tm_cavity_2d(chat=0.0, steps=150)
+    else:
+        w = configs.tm111_3d(n_side=10, chat=0.0, steps=60)
+    s = Solver.from_workload(w, precision="f64")
+    for lds in (1, 0):
+        s.set_variant(block=256, xcd=1, lds=lds)
+        st0 = s.state(w.E0, w.H0)
+        s.half(st0, 0)
+        H1 = s.to_original(st0.Hb[1 - st0.cur])[:, :s.fh]
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        s.half(st, 0)
+        Hn = st.Hb[1 - st.cur]
+        back = State([st.E.clone(), torch.zeros_like(st.E)], [(-Hn).contiguous(), torch.zeros_like(Hn)], 0, None)
+        s.step(back, w.steps)
+        E, H = s.E_original(back), s.H_original(back)
+        eE = np.abs(E - w.E0).max() / np.abs(w.E0).max()
+        eH = np.abs(H + H1).max() / np.abs(H1).max()
+        _announce(f"  lds={lds}: E {eE:.2e} H {eH:.2e}")
+        assert eE < 1e-10 and eH < 1e-10

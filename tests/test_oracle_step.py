@@ -319,3 +319,32 @@ def test_wall_projection_on_axis_normals_is_the_axis_rule():
     out = step.wall_project(E[:1], np.ones((1, 2)), n)
     assert abs(out[0, 0] * 0.8 - out[0, 1] * 0.6) < 1e-15
     assert abs((out[0] * n[0]).sum() - (E[0] * n[0]).sum()) < 1e-15
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_leapfrog_is_time_reversible_without_hyperviscosity(dim):
+    # Time reversal of the interleaved leapfrog (eq. 19 with gamma = 0): if
+    # (E^n, H^n) solve the scheme, so do E~^m = E^{T-m}, H~^m = -H^{T+1-m}.
+    # Running T steps from (E^T, -H^{T+1}) must give back (E^0, -H^1); an E
+    # update reading the old H, or a curl with a wrong sign in one half,
+    # breaks the identity.  PEC masks are projections that commute with it.
+    if dim == 2:
+        xyz, flags, h = nodes.jittered_grid((15, 15), seed=21)
+        op = _op(xyz, 12, 2, 31, 2)
+        E0 = (np.sin(math.pi * xyz[:, 0]) * np.sin(2 * math.pi * xyz[:, 1]))[:, None]
+        H0 = np.stack([np.cos(3 * xyz[:, 1]), np.sin(2 * xyz[:, 0] + xyz[:, 1])], 1)
+    else:
+        xyz, flags, h = nodes.jittered_grid((7, 7, 7), seed=22)
+        op = _op(xyz, 35, 2, 71, 2)
+        E0 = np.stack([np.sin(math.pi * xyz[:, 1]), np.cos(xyz[:, 2]), xyz[:, 0] * xyz[:, 1]], 1)
+        H0 = np.stack([np.cos(2 * xyz[:, 2]), xyz[:, 0] ** 2, np.sin(xyz[:, 1] - xyz[:, 0])], 1)
+    keep = step.pec_keep(flags, dim)
+    E0 = E0 * keep
+    dt = configs.SC * h
+    T = 60
+    E, H, _, _ = step.run(E0, H0, op, op, dt, T, 0.0, dt, keep)
+    H_next = step.h_update(E, H, op, dt, 0.0)                       # H^{T+1}
+    H1 = step.h_update(E0, H0, op, dt, 0.0)                         # H^1
+    Eb, Hb, _, _ = step.run(E, -H_next, op, op, dt, T, 0.0, dt, keep)
+    assert np.abs(Eb - E0).max() <= 1e-11 * np.abs(E0).max()
+    assert np.abs(Hb + H1).max() <= 1e-11 * np.abs(H1).max()
