@@ -570,8 +570,13 @@ def main():
         # error against the Bessel solution: TM_01 (TMz) and TE_01 (TEz, wall
         # nodes keep the normal component of E)
         from synth import fields as _fields
+        # and the coaxial cavity 0.5 <= r <= 1 (a conducting cylinder inside)
+        coax = {pol: (lambda h, pol=pol: configs.coax_2d(pol=pol, h=h),
+                      lambda x, te, th, pol=pol: _fields.coax_mode(x, te, th, pol=pol)) for pol in ("TM", "TE")}
         for key, make, exact in (("tm01_disk", configs.tm01_disk, _fields.tm01_disk),
-                                 ("te01_disk", configs.te01_disk, _fields.te01_disk)):
+                                 ("te01_disk", configs.te01_disk, _fields.te01_disk),
+                                 ("coax_tm01", coax["TM"][0], coax["TM"][1]),
+                                 ("coax_te01", coax["TE"][0], coax["TE"][1])):
             wk = make(h=0.0025)
             sk, tk = setup_w(wk, "f32")
             ak = sk.state(wk.E0, wk.H0)

@@ -267,6 +267,26 @@ def te01_disk(h=0.02, R=1.0, n=12, m=2, alpha=2, chat=1e-3, periods=1.0, seed=9)
     return w
 
 
+def coax_2d(pol="TM", h=0.02, a=0.5, b=1.0, n=12, m=2, alpha=2, chat=1e-3, periods=1.0, seed=11):
+    """Coaxial PEC cavity a <= r <= b (a conducting cylinder inside the
+    domain) with its first circularly symmetric mode (TM_01 in TMz, TE_01 in
+    TEz) for ``periods`` periods; in TEz every wall node carries the radial
+    unit normal."""
+    xyz, flags, hm = _nodes.disk_nodes(b, h, seed=seed, R_in=a)
+    w = Workload(f"coax_{pol.lower()}", 2, xyz, flags, h, n, m, alpha, _hv_default(2, alpha), chat, 0,
+                 lo=(-b, -b), hi=(b, b), pol=pol)
+    if pol == "TE":
+        wall = flags != 0
+        nrm = np.zeros((w.N, 2))
+        nrm[wall] = xyz[wall] / np.hypot(xyz[wall, 0], xyz[wall, 1])[:, None]
+        w.normals = nrm
+    E0, H0, om = _fields.coax_mode(xyz, 0.0, -0.5 * w.dt, pol=pol, a=a, b=b)
+    w.E0, w.H0 = E0, H0
+    w.steps = int(round(periods * 2 * math.pi / om / w.dt))
+    w.meta.update(a=a, b=b, omega=om, h_mean=hm)
+    return w
+
+
 REGISTRY = {
     "tm_cavity_2d": tm_cavity_2d,
     "pulse_2d": pulse_2d,
@@ -278,6 +298,7 @@ REGISTRY = {
     "tm01_disk": tm01_disk,
     "te_cavity_2d": te_cavity_2d,
     "te01_disk": te01_disk,
+    "coax_2d": coax_2d,
 }
 
 

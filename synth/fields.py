@@ -135,6 +135,51 @@ def te01_disk(xyz, t_e, t_h, R=1.0, centre=(0.0, 0.0), eps0=1.0, mu0=1.0):
     return E, Hz, om
 
 
+def coax_wavenumber(a, b, pol):
+    """Smallest k > 0 of the first circularly symmetric mode of the coaxial
+    cavity a <= r <= b: TM_01 needs Z(kb) = 0 for Z(r) = J0(kr) Y0(ka) -
+    J0(ka) Y0(kr); TE_01 needs Z'(b) = 0 for Z(r) = J0(kr) Y1(ka) - J1(ka)
+    Y0(kr), i.e. J1(kb) Y1(ka) - J1(ka) Y1(kb) = 0."""
+    from scipy import optimize, special
+    if pol == "TM":
+        f = lambda k: special.j0(k * b) * special.y0(k * a) - special.j0(k * a) * special.y0(k * b)
+    else:
+        f = lambda k: special.j1(k * b) * special.y1(k * a) - special.j1(k * a) * special.y1(k * b)
+    ks = np.linspace(0.05, 10.0 * math.pi / (b - a), 4000)
+    v = f(ks)
+    i = int(np.nonzero(np.sign(v[1:]) != np.sign(v[:-1]))[0][0])
+    return optimize.brentq(f, ks[i], ks[i + 1], xtol=1e-15, rtol=1e-15, maxiter=200)
+
+
+def coax_mode(xyz, t_e, t_h, pol="TM", a=0.5, b=1.0, eps0=1.0, mu0=1.0):
+    """First circularly symmetric mode of the coaxial PEC cavity a <= r <= b.
+
+    TM_01 (TMz): Ez = Z(r) cos(omega t), Z as in ``coax_wavenumber``;
+    Faraday's law gives H = (Z'(r) / (mu0 omega)) (-sin theta, cos theta)
+    sin(omega t).  TE_01 (TEz): Hz = Z(r) cos(omega t); Ampere's law gives
+    E = (Z'(r) / (eps0 omega)) (sin theta, -cos theta) sin(omega t), which
+    vanishes on both walls.  Returns (E at t_e, H at t_h, omega) in the
+    polarisation's layout (TM: [N, 1], [N, 2]; TE: [N, 2], [N, 1]).
+    """
+    from scipy import special
+    c0, _ = consts(eps0, mu0)
+    k = coax_wavenumber(a, b, pol)
+    om = c0 * k
+    x, y = xyz[:, 0], xyz[:, 1]
+    r = np.hypot(x, y)
+    st, ct = y / r, x / r
+    if pol == "TM":
+        Z = special.j0(k * r) * special.y0(k * a) - special.j0(k * a) * special.y0(k * r)
+        dZ = k * (-special.j1(k * r) * special.y0(k * a) + special.j0(k * a) * special.y1(k * r))
+        E = (Z * math.cos(om * t_e))[:, None]
+        amp = dZ / (mu0 * om) * math.sin(om * t_h)
+        return E, np.stack([-amp * st, amp * ct], axis=1), om
+    Z = special.j0(k * r) * special.y1(k * a) - special.j1(k * a) * special.y0(k * r)
+    dZ = k * (-special.j1(k * r) * special.y1(k * a) + special.j1(k * a) * special.y1(k * r))
+    amp = dZ / (eps0 * om) * math.sin(om * t_e)
+    return np.stack([amp * st, -amp * ct], axis=1), (Z * math.cos(om * t_h))[:, None], om
+
+
 def in_frame(H, theta):
     """Components of the 2D vectors H [N, 2] in the frame with axes
     u_1 = (cos theta, sin theta), u_2 = (-sin theta, cos theta)."""

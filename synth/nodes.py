@@ -269,20 +269,27 @@ def line_seeded_periodic(L=200.0, h=1.0, r_factor=0.794, seed=3, stream=0, round
     return xyz, np.zeros(xyz.shape[0], np.uint8), h, np.arange(nl)
 
 
-def disk_nodes(R=1.0, h=0.02, centre=(0.0, 0.0), r_factor=0.794, seed=9, stream=0, rounds=12):
-    """Scattered nodes in the disk |x - centre| <= R with a curved wall.
+def disk_nodes(R=1.0, h=0.02, centre=(0.0, 0.0), r_factor=0.794, seed=9, stream=0, rounds=12, R_in=0.0):
+    """Scattered nodes in the disk |x - centre| <= R with a curved wall, or in
+    the annulus R_in <= |x - centre| <= R (a conducting cylinder inside).
 
-    The wall nodes are round(2 pi R / h) equispaced points on the circle
-    (flag FACE_XLO: in 2D any wall flag marks a node on which Ez vanishes);
-    interior darts inside the circle are accepted at least r = r_factor h
-    from every accepted node.  Returns (xyz [N, 2], flags [N], h_mean) with
-    h_mean = sqrt(pi R^2 / N).
+    The wall nodes are round(2 pi R / h) equispaced points on the circle (and
+    round(2 pi R_in / h) on the inner one, after them; flag FACE_XLO: in 2D
+    any wall flag marks a node on which Ez vanishes); darts between the
+    circles are accepted at least r = r_factor h from every accepted node.
+    Returns (xyz [N, 2], flags [N], h_mean) with h_mean = sqrt(area / N).
     """
     cx, cy = float(centre[0]), float(centre[1])
     nb = int(round(2.0 * math.pi * R / h))
     th = 2.0 * math.pi * np.arange(nb) / nb
     bx = cx + R * np.cos(th)
     by = cy + R * np.sin(th)
+    if R_in > 0.0:
+        ni = int(round(2.0 * math.pi * R_in / h))
+        ti = 2.0 * math.pi * np.arange(ni) / ni
+        bx = np.concatenate([bx, cx + R_in * np.cos(ti)])
+        by = np.concatenate([by, cy + R_in * np.sin(ti)])
+        nb += ni
     r = r_factor * h
     cs = r / math.sqrt(2.0)
     nc = int(math.ceil(2.0 * R / cs)) + 1
@@ -312,7 +319,8 @@ def disk_nodes(R=1.0, h=0.02, centre=(0.0, 0.0), r_factor=0.794, seed=9, stream=
             counter += 1
             qx = x0 + (cxs + ux) * cs
             qy = y0 + (cys + uy) * cs
-            ok = (qx - cx) ** 2 + (qy - cy) ** 2 < R * R
+            d2 = (qx - cx) ** 2 + (qy - cy) ** 2
+            ok = (d2 < R * R) & (d2 > R_in * R_in)
             for dy in range(-2, 3):
                 for dx in range(-2, 3):
                     j = occ[cys + 2 + dy, cxs + 2 + dx]
@@ -331,4 +339,4 @@ def disk_nodes(R=1.0, h=0.02, centre=(0.0, 0.0), r_factor=0.794, seed=9, stream=
     xyz = np.stack([allx, ally], axis=1)
     flags = np.zeros(xyz.shape[0], np.uint8)
     flags[:nb] = FACE_XLO
-    return xyz, flags, math.sqrt(math.pi * R * R / xyz.shape[0])
+    return xyz, flags, math.sqrt(math.pi * (R * R - R_in * R_in) / xyz.shape[0])

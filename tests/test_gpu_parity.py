@@ -443,6 +443,38 @@ def test_te01_circular_cavity_curved_wall():
         assert eE < 1.05 * eEo + 1e-6 and eH < 1.05 * eHo + 1e-6
 
 
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_coaxial_cavity_inner_conductor(pol):
+    # an irregular PEC body: the coaxial cavity 0.5 <= r <= 1 (4014 nodes,
+    # 1 1/8 periods), TM_01 / TE_01; oracle weights on the staged and global
+    # kernels, end to end FP64 / FP32 against the oracle and the closed form
+    _announce(f"coaxial cavity {pol}")
+    w = configs.coax_2d(pol=pol, h=0.025, periods=1.125)
+    oh, oe = osetup.operators(w)
+    Eo, Ho, _, _ = osetup.run_workload(w, oh, oe)
+    Ea, Ha, _ = fields.coax_mode(w.xyz, w.steps * w.dt, (w.steps - 0.5) * w.dt, pol=pol)
+    eEo, eHo = ostep.linf_errors(Eo, Ho, Ea, Ha)
+    s = Solver.from_workload(w, precision="f64")
+    _inject(s, oh)
+    for lds in (1, 0):
+        s.set_variant(block=256, xcd=1, lds=lds)
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        e = max(ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho))
+        _announce(f"  injected f64 lds={lds} vs oracle {e:.2e}")
+        assert e < 1e-12
+    for prec, tol in (("f64", 1e-9), ("f32", 1e-5)):
+        s = Solver.from_workload(w, precision=prec)
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        E, H = s.E_original(st), s.H_original(st)
+        e = max(ostep.rel_l2(E, Eo), ostep.rel_l2(H, Ho))
+        eE, eH = ostep.linf_errors(E, H, Ea, Ha)
+        _announce(f"  {prec} vs oracle {e:.2e}; vs closed form E {eE:.2e} ({eEo:.2e}) H {eH:.2e} ({eHo:.2e})")
+        assert e < tol
+        assert eE < 1.05 * eEo + 1e-6 and eH < 1.05 * eHo + 1e-6
+
+
 def test_te_polarisation_cavity_and_periodic():
     # TEz (Ex, Ey, Hz): TE_11 mode of the PEC square (51 x 51, 1 1/8 periods,
     # a phase at which E and Hz are both of order one; eps0 != mu0) with

@@ -348,3 +348,28 @@ def test_leapfrog_is_time_reversible_without_hyperviscosity(dim):
     Eb, Hb, _, _ = step.run(E, -H_next, op, op, dt, T, 0.0, dt, keep)
     assert np.abs(Eb - E0).max() <= 1e-11 * np.abs(E0).max()
     assert np.abs(Hb + H1).max() <= 1e-11 * np.abs(H1).max()
+
+
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_coaxial_cavity_converges(pol):
+    # an irregular PEC body: the annulus 0.5 <= r <= 1 between two conducting
+    # cylinders, first circularly symmetric mode (TM_01: Ez = J0 Y0 - J0 Y0
+    # cross product vanishing on both circles; TE_01: E azimuthal, vanishing
+    # on both walls) after 1 1/8 periods, against its closed form
+    res = []
+    for h in (0.05, 0.025):
+        w = configs.coax_2d(pol=pol, h=h, periods=1.125)
+        oh, oe = setup.operators(w)
+        E, H, _, _ = setup.run_workload(w, oh, oe)
+        Ea, Ha, _ = fields.coax_mode(w.xyz, w.steps * w.dt, (w.steps - 0.5) * w.dt, pol=pol)
+        wall = w.flags > 0
+        if pol == "TM":
+            assert np.abs(E[wall]).max() == 0.0
+        else:
+            tang = -E[wall, 0] * w.normals[wall, 1] + E[wall, 1] * w.normals[wall, 0]
+            assert np.abs(tang).max() < 1e-15
+        res.append(step.linf_errors(E, H, Ea, Ha) + (w.meta["h_mean"],))
+    (eE1, eH1, h1), (eE2, eH2, h2) = res
+    assert eE1 < 4e-3 and eH1 < 4e-3
+    assert math.log(eE1 / eE2) / math.log(h1 / h2) >= 1.5
+    assert math.log(eH1 / eH2) / math.log(h1 / h2) >= 1.5
