@@ -219,16 +219,18 @@ int rbffd_plan_create(const rbffd_params* p, int64_t N, const double* xyz_host,
                       const uint8_t* flagsH_host, rbffd_plan** out);
 int rbffd_plan_sizes(const rbffd_plan* plan, rbffd_sizes* out);
 
-/* Curved PEC walls in the TEz polarisation.  normals_host [N][2] doubles in
- * the caller's node order: a unit outward (or inward) normal on each node of
- * a curved wall, (0, 0) elsewhere.  After every E update a node with a normal
- * keeps only the normal component of (Ex, Ey), E <- (E . n) n, so the
- * tangential E vanishes on the wall (nodes without one follow the axis rule
- * of their flags).  Host-only; call between rbffd_plan_create and
- * rbffd_weights (RBFFD_ESTATE afterwards); NULL clears.  RBFFD_ENOTSUP for
- * plans other than TEz with PEC walls; RBFFD_EINVAL for a normal that is not
- * a unit vector (|n|^2 - 1 beyond 1e-9) or sits on a node without a wall
- * flag.  The plan copies the data. */
+/* Curved PEC walls where E is a vector: the TEz polarisation and 3D.
+ * normals_host [N][dim] doubles in the caller's node order: a unit outward
+ * (or inward) normal on each node of a curved wall, zero elsewhere.  After
+ * every E update a node with a normal keeps only the normal component of E,
+ * E <- (E . n) n, so the tangential E vanishes on the wall (nodes without one
+ * follow the axis rule of their flags); a 3D soft source on such a node adds
+ * its projection.  (TMz needs none: Ez is tangential to every in-plane wall.)
+ * Host-only; call between rbffd_plan_create and rbffd_weights (RBFFD_ESTATE
+ * afterwards); NULL clears.  RBFFD_ENOTSUP for plans other than collocated
+ * TEz or 3D with PEC walls; RBFFD_EINVAL for a normal that is not a unit
+ * vector (|n|^2 - 1 beyond 1e-9) or sits on a node without a wall flag.  The
+ * plan copies the data. */
 int rbffd_set_wall_normals(rbffd_plan* plan, const double* normals_host);
 void rbffd_plan_destroy(rbffd_plan* plan);
 const char* rbffd_strerror(int code);

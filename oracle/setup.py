@@ -67,5 +67,6 @@ def run_workload(w, op_h, op_e, steps=None, energy_every=0, use_eps=True, src=Tr
         s = (w.src_node, w.src_amp, w.src_wave)
     r = w.rcv_node if (rcv and w.rcv_node is not None) else None
     h_h = w.h_h if w.h_h is not None else w.h
+    nrm = w.normals if (w.bc == "PEC" and w.dim == 3) else None
     return _step.run(w.E0, w.H0, op_h, op_e, w.dt, steps, gamma, kappa, keep, mu0=w.mu0,
-                     eps0=w.eps0, h_e=w.h, h_h=h_h, energy_every=energy_every, src=s, rcv=r)
+                     eps0=w.eps0, h_e=w.h, h_h=h_h, energy_every=energy_every, src=s, rcv=r, normals=nrm)

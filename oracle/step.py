@@ -75,11 +75,12 @@ def h_update(E, H, op, a, gamma, rows=None):
     return np.stack([Hc[:, c] - a * (curl[c] - gamma * D(hw, hi, H[:, c])) for c in range(3)], axis=1)
 
 
-def e_update(E, Hn, op, kappa, gamma, keep, src=None, rows=None):
+def e_update(E, Hn, op, kappa, gamma, keep, src=None, rows=None, normals=None):
     """E^{n+1} from E^n and H^{n+1} (last line of eq. 19), then PEC.
 
     src = (nodes [S], values [S]) adds values at nodes after the bracket.
     ``rows`` as in h_update (keep and an array kappa are then per row).
+    normals (3D) [N, 3]: unit normals of curved-wall nodes (see wall_project).
     """
     cw, ci = op["curl_w"], op["curl_idx"]
     hw, hi = op["hv_w"], op["hv_idx"]
@@ -98,7 +99,7 @@ def e_update(E, Hn, op, kappa, gamma, keep, src=None, rows=None):
         nodes, vals = src
         for s in range(len(nodes)):
             out[nodes[s], 0 if out.shape[1] == 1 else 2] += vals[s]
-    return out * keep
+    return wall_project(out, keep, normals)
 
 
 # ---------------------------------------------------------------------------
@@ -135,11 +136,12 @@ def te_e_update(E, Hz_new, op, kappa, gamma, keep, rows=None, normals=None):
 
 
 def wall_project(E, keep, normals=None):
-    """PEC on in-plane E [N, 2]: the tangential part vanishes on the wall.
+    """PEC on the vector E [N, 2] (TEz) or [N, 3] (3D): the tangential part
+    vanishes on the wall.
 
     Component c survives where keep[:, c] = 1 (walls normal to an axis); at a
     node with a unit normal n (a curved wall) only the normal component
-    survives, E <- (E . n) n.  ``normals`` [N, 2] is zero off the wall."""
+    survives, E <- (E . n) n.  ``normals`` [N, 2 or 3] is zero off the wall."""
     out = E * keep
     if normals is not None:
         sel = np.abs(normals).sum(axis=1) > 0
@@ -202,7 +204,7 @@ def rel_l2(x, ref):
 
 
 def run(E, H, op_h, op_e, dt, steps, gamma, kappa, keep, mu0=1.0, eps0=1.0,
-        h_e=None, h_h=None, energy_every=0, src=None, rcv=None):
+        h_e=None, h_h=None, energy_every=0, src=None, rcv=None, normals=None):
     """Advance ``steps`` full leapfrog steps.
 
     kappa: scalar or [N_E] array (dt / (eps0 eps_r)).
@@ -224,7 +226,7 @@ def run(E, H, op_h, op_e, dt, steps, gamma, kappa, keep, mu0=1.0, eps0=1.0,
         s = None
         if src is not None:
             s = (src[0], src[1] * src[2][n])
-        E = e_update(E, Hn, op_e, kappa, gamma, keep, s)
+        E = e_update(E, Hn, op_e, kappa, gamma, keep, s, normals=normals)
         H = Hn
         if rcv is not None:
             traces.append(E[rcv, -1].copy())

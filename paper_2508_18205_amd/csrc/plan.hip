@@ -79,8 +79,8 @@ void layout_set(Bump& b, NodeSet& S, int dim, bool is_e, bool normals) {
     S.inv = b.take<int32_t>(S.N);
     S.xyz = b.take<double>(S.N * dim);
     S.emask = is_e ? b.take<uint8_t>(S.N) : nullptr;
-    S.nrm_in = normals ? b.take<double>(S.N * 2) : nullptr;
-    S.nrm = normals ? b.take<double>(S.N * 2) : nullptr;
+    S.nrm_in = normals ? b.take<double>(S.N * dim) : nullptr;
+    S.nrm = normals ? b.take<double>(S.N * dim) : nullptr;
 }
 
 void layout_block(Bump& b, OpBlock& o, int dim, int wb, int K, bool adjoint) {
@@ -130,8 +130,9 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int K, bool adjoint) {
 int64_t layout_arena(rbffd_plan* p, char* base, int64_t* ws, int64_t* adj_ws) {
     Bump b{base};
     const int wb = weight_elem_bytes(p->p.wdtype);
-    const bool te_walls = p->p.pol == RBFFD_POL_TE && p->p.bc == RBFFD_BC_PEC;
-    layout_set(b, p->E, p->dim, true, te_walls);
+    // curved walls need per-node normals where E is a vector: TEz and 3D
+    const bool curved = p->p.bc == RBFFD_BC_PEC && (p->p.pol == RBFFD_POL_TE || p->dim == 3);
+    layout_set(b, p->E, p->dim, true, curved);
     if (!p->collocated) layout_set(b, p->H, p->dim, false, false);
     layout_block(b, p->opH, p->dim, wb, p->K, p->p.adjoint != 0);
     if (!p->collocated) layout_block(b, p->opE, p->dim, wb, p->K, false);
@@ -283,23 +284,31 @@ extern "C" int rbffd_plan_create(const rbffd_params* prm, int64_t N, const doubl
 
 extern "C" int rbffd_set_wall_normals(rbffd_plan* p, const double* normals_host) {
     if (!p) return RBFFD_EINVAL;
-    if (p->p.pol != RBFFD_POL_TE || p->p.bc != RBFFD_BC_PEC)
-        return set_err(p, RBFFD_ENOTSUP, "wall normals apply to TEz plans with PEC walls");
+    if (p->p.bc != RBFFD_BC_PEC || !(p->p.pol == RBFFD_POL_TE || p->dim == 3) || !p->collocated)
+        return set_err(p, RBFFD_ENOTSUP, "wall normals apply to collocated TEz or 3D plans with PEC walls");
     if (p->ready) return set_err(p, RBFFD_ESTATE, "wall normals must be set before rbffd_weights");
     const int64_t N = p->E.N;
+    const int d = p->dim;
     if (!normals_host) {
         p->E.nrm_host.clear();
         return RBFFD_OK;
     }
     for (int64_t i = 0; i < N; ++i) {
-        const double nx = normals_host[2 * i], ny = normals_host[2 * i + 1];
-        if (nx == 0.0 && ny == 0.0) continue;
-        if (!std::isfinite(nx) || !std::isfinite(ny) || std::fabs(nx * nx + ny * ny - 1.0) > 1e-9)
+        double n2 = 0.0;
+        bool finite = true, zero = true;
+        for (int k = 0; k < d; ++k) {
+            const double v = normals_host[d * i + k];
+            finite = finite && std::isfinite(v);
+            zero = zero && v == 0.0;
+            n2 += v * v;
+        }
+        if (zero) continue;
+        if (!finite || std::fabs(n2 - 1.0) > 1e-9)
             return set_err(p, RBFFD_EINVAL, "wall normal of node " + std::to_string(i) + " is not a unit vector");
         if (p->E.flags_host[i] == 0)
             return set_err(p, RBFFD_EINVAL, "node " + std::to_string(i) + " has a wall normal but no wall flag");
     }
-    p->E.nrm_host.assign(normals_host, normals_host + 2 * N);
+    p->E.nrm_host.assign(normals_host, normals_host + d * N);
     return RBFFD_OK;
 }
 

@@ -234,6 +234,15 @@ __global__ void k_internal_nodes(const double* xyz_in, const uint8_t* flags_in, 
         keep = 7;
         for (int k = 0; k < 3; ++k)
             if (f & (3u << (2 * k))) keep &= (uint8_t)(1u << k);   // only the normal component survives
+        if (nrm) {                          // curved wall: project on the given normal
+            bool any = false;
+            for (int k = 0; k < 3; ++k) {
+                const double v = nrm_in[3 * o + k];
+                nrm[3 * p + k] = v;
+                any = any || v != 0.0;
+            }
+            if (any) keep |= 8;
+        }
     }
     emask[p] = keep;
 }
@@ -986,8 +995,9 @@ int setup_nodes_and_stencils(rbffd_plan* p, void* wsp, hipStream_t st) {
     HIPCHK(p, hipMemcpyAsync(p->E.xyz_in, p->E.xyz_host.data(), p->E.N * d * 8, hipMemcpyHostToDevice, st));
     HIPCHK(p, hipMemcpyAsync(p->E.flags_in, p->E.flags_host.data(), p->E.N, hipMemcpyHostToDevice, st));
     if (p->E.nrm_in) {
-        if (p->E.nrm_host.empty()) HIPCHK(p, hipMemsetAsync(p->E.nrm_in, 0, p->E.N * 16, st));
-        else HIPCHK(p, hipMemcpyAsync(p->E.nrm_in, p->E.nrm_host.data(), p->E.N * 16, hipMemcpyHostToDevice, st));
+        const size_t nb = (size_t)p->E.N * d * 8;
+        if (p->E.nrm_host.empty()) HIPCHK(p, hipMemsetAsync(p->E.nrm_in, 0, nb, st));
+        else HIPCHK(p, hipMemcpyAsync(p->E.nrm_in, p->E.nrm_host.data(), nb, hipMemcpyHostToDevice, st));
     }
     int rc = build_search(p, p->E, se, st);
     if (rc) return rc;

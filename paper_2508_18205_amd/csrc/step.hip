@@ -43,7 +43,7 @@ struct SA {
     double dt, eps0;
     const void* eps_r;    // per-node eps_r (double for FP64 fields, else float) or null
     const uint8_t* emask;
-    const double* wnrm;   // [N][2] unit wall normals (TEz curved walls; emask bit 3)
+    const double* wnrm;   // [N][dim] unit wall normals (TEz and 3D curved walls; emask bit 3)
     // TEz: the 2D kernels with the fields' roles exchanged.  te = 1: the
     // vector kernel updates (Ex, Ey) from Hz with factor -kappa_i and the wall
     // mask; nomask = 1: the scalar kernel updates Hz (no wall mask)
@@ -58,6 +58,23 @@ struct SA {
 // PEC on the in-plane E of the TEz polarisation: bit 0 / 1 of the mask keeps
 // Ex / Ey (walls normal to an axis); bit 3 marks a curved-wall node with unit
 // normal n = wn[i], where only the normal component survives: E <- (E . n) n
+// The same for the 3D E: bits 0..2 keep Ex, Ey, Ez (faces normal to an axis),
+// bit 3 projects on the unit normal wn[i] (curved wall)
+template <typename TC>
+__device__ __forceinline__ void wall3(uint8_t m, const double* wn, int64_t i, TC& x, TC& y, TC& z) {
+    if (m & 8) {
+        const TC nx = (TC)wn[3 * i], ny = (TC)wn[3 * i + 1], nz = (TC)wn[3 * i + 2];
+        const TC en = x * nx + y * ny + z * nz;
+        x = en * nx;
+        y = en * ny;
+        z = en * nz;
+    } else {
+        x = (m & 1) ? x : (TC)0;
+        y = (m & 2) ? y : (TC)0;
+        z = (m & 4) ? z : (TC)0;
+    }
+}
+
 template <typename TC>
 __device__ __forceinline__ void te_wall(uint8_t m, const double* wn, int64_t i, TC& x, TC& y) {
     if (m & 8) {
@@ -600,10 +617,10 @@ __global__ __launch_bounds__(512) void k_e3(SA<TS, TW> a) {
     }
     if (i < a.N) {
         const TC k = kappa_of(a, i), G = (TC)a.g;
-        const uint8_t m = a.emask[i];
-        const TC nx = (m & 1) ? ex0 + k * ((yHz - zHy) + G * vx) : (TC)0;
-        const TC ny = (m & 2) ? ey0 + k * ((zHx - xHz) + G * vy) : (TC)0;
-        const TC nz = (m & 4) ? ez0 + k * ((xHy - yHx) + G * vz) : (TC)0;
+        TC nx = ex0 + k * ((yHz - zHy) + G * vx);
+        TC ny = ey0 + k * ((zHx - xHz) + G * vy);
+        TC nz = ez0 + k * ((xHy - yHx) + G * vz);
+        wall3(a.emask[i], a.wnrm, i, nx, ny, nz);
         S::st3(a.out, i, nx, ny, nz);
     }
 }
@@ -1038,10 +1055,10 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
     }
     if (i < a.N) {
         const TC k = kappa_of(a, i), G = (TC)a.g;
-        const uint8_t m = a.emask[i];
-        const TC nx = (m & 1) ? ex0 + k * ((yHz - zHy) + G * vx) : (TC)0;
-        const TC ny = (m & 2) ? ey0 + k * ((zHx - xHz) + G * vy) : (TC)0;
-        const TC nz = (m & 4) ? ez0 + k * ((xHy - yHx) + G * vz) : (TC)0;
+        TC nx = ex0 + k * ((yHz - zHy) + G * vx);
+        TC ny = ey0 + k * ((zHx - xHz) + G * vy);
+        TC nz = ez0 + k * ((xHy - yHx) + G * vz);
+        wall3(a.emask[i], a.wnrm, i, nx, ny, nz);
         S::st3(a.out, i, nx, ny, nz);
     }
 }
@@ -1192,11 +1209,11 @@ __global__ __launch_bounds__(256) void k_e3p(SA<TS, TW> a) {
     if (live) hv_sums3<TC, TW>(sF, pl, ph, a.V4, e0, v);
     if (live && i < a.N) {
         const TC k = kappa_of(a, i), G = (TC)a.g;
-        const uint8_t m = a.emask[i];
         // c = (xHy, xHz, yHx, yHz, zHx, zHy)
-        const TC nx = (m & 1) ? e0[0] + k * ((c[3] - c[5]) + G * v[0]) : (TC)0;
-        const TC ny = (m & 2) ? e0[1] + k * ((c[4] - c[1]) + G * v[1]) : (TC)0;
-        const TC nz = (m & 4) ? e0[2] + k * ((c[0] - c[2]) + G * v[2]) : (TC)0;
+        TC nx = e0[0] + k * ((c[3] - c[5]) + G * v[0]);
+        TC ny = e0[1] + k * ((c[4] - c[1]) + G * v[1]);
+        TC nz = e0[2] + k * ((c[0] - c[2]) + G * v[2]);
+        wall3(a.emask[i], a.wnrm, i, nx, ny, nz);
         S::st3(a.out, i, nx, ny, nz);
     }
 }
@@ -1204,8 +1221,8 @@ __global__ __launch_bounds__(256) void k_e3p(SA<TS, TW> a) {
 // ---- per-step auxiliaries (read the device step counter) --------------------
 // src: E[node] += amp * wave[n * S + s] after the bracket (PEC nodes stay 0)
 template <typename TS>
-__global__ void k_source(TS* E, int FE, int comp, const uint8_t* emask, int S, const int32_t* node, const void* amp,
-                         const void* wave, const int32_t* ctr, int step_base) {
+__global__ void k_source(TS* E, int FE, int comp, const uint8_t* emask, const double* wn, int S, const int32_t* node,
+                         const void* amp, const void* wave, const int32_t* ctr, int step_base) {
     using St = Store<TS>;
     using TC = typename St::C;
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -1216,6 +1233,14 @@ __global__ void k_source(TS* E, int FE, int comp, const uint8_t* emask, int S, c
         TC v;
         if (sizeof(TC) == 8) v = ((const double*)amp)[s] * ((const double*)wave)[n * S + s];
         else v = ((const float*)amp)[s] * ((const float*)wave)[n * S + s];
+        if (emask[i] & 8) {
+            // curved 3D wall: E is already projected on the normal n, so adding
+            // the projected source v n_comp n keeps (E + v e_comp) projected
+            const double* n = wn + 3 * i;
+            for (int c = 0; c < 3; ++c)
+                St::st1(E, i * FE + c, St::ld1(E, i * FE + c) + v * (TC)n[comp] * (TC)n[c]);
+            continue;
+        }
         const TC cur = St::ld1(E, e);
         St::st1(E, e, ((emask[i] >> comp) & 1) ? cur + v : (TC)0);
     }
@@ -1538,15 +1563,15 @@ void full_step(const rbffd_plan* p, const rbffd_fields* f, int c, const rbffd_ru
         switch (p->p.fdtype) {
             case RBFFD_F64:
                 hipLaunchKernelGGL(k_source<double>, dim3(1), dim3(64), 0, st, (double*)f->E[o], p->FE, comp, p->E.emask,
-                                   a->n_src, a->src_node, a->src_amp, a->src_wave, w.ctr, a->step0);
+                                   p->E.nrm, a->n_src, a->src_node, a->src_amp, a->src_wave, w.ctr, a->step0);
                 break;
             case RBFFD_F32:
                 hipLaunchKernelGGL(k_source<float>, dim3(1), dim3(64), 0, st, (float*)f->E[o], p->FE, comp, p->E.emask,
-                                   a->n_src, a->src_node, a->src_amp, a->src_wave, w.ctr, a->step0);
+                                   p->E.nrm, a->n_src, a->src_node, a->src_amp, a->src_wave, w.ctr, a->step0);
                 break;
             default:
                 hipLaunchKernelGGL(k_source<bf16s>, dim3(1), dim3(64), 0, st, (bf16s*)f->E[o], p->FE, comp,
-                                   p->E.emask, a->n_src, a->src_node, a->src_amp, a->src_wave, w.ctr, a->step0);
+                                   p->E.emask, p->E.nrm, a->n_src, a->src_node, a->src_amp, a->src_wave, w.ctr, a->step0);
         }
     }
     if (a->n_rcv > 0) {

@@ -94,7 +94,7 @@ class Solver:
         self.plan = plan
         if normals is not None:
             nrm = np.ascontiguousarray(normals, dtype=np.float64)
-            assert nrm.shape == (self.xyz.shape[0], 2)
+            assert nrm.shape == (self.xyz.shape[0], dim)
             check(self.lib.rbffd_set_wall_normals(plan, nrm.ctypes.data), plan, "set_wall_normals")
         s = _abi.Sizes()
         check(self.lib.rbffd_plan_sizes(plan, C.byref(s)), plan, "plan_sizes")

@@ -70,7 +70,7 @@ class Workload:
     # extras
     pol: str = "TM"           # 2D polarisation: TM (Ez, Hx, Hy) | TE (Ex, Ey, Hz)
     frame_angle: float = 0.0  # 2D: angle of the frame the curl is discretised in
-    normals: Optional[np.ndarray] = None       # [N, 2] unit wall normals (curved TEz walls), 0 elsewhere
+    normals: Optional[np.ndarray] = None       # [N, d] unit wall normals (curved TEz / 3D walls), 0 elsewhere
     K: int = 1
     E0_batch: Optional[np.ndarray] = None      # [K, N, FE]
     eps_r: Optional[np.ndarray] = None
@@ -287,6 +287,23 @@ def coax_2d(pol="TM", h=0.02, a=0.5, b=1.0, n=12, m=2, alpha=2, chat=1e-3, perio
     return w
 
 
+def sphere_3d(h=0.1, R=1.0, n=35, m=2, alpha=2, chat=1e-4, periods=1.0, seed=13):
+    """PEC sphere (curved 3D wall) with its lowest azimuthal mode for
+    ``periods`` periods; every wall node carries the outward unit normal."""
+    xyz, flags, hm = _nodes.ball_nodes(R, h, seed=seed)
+    w = Workload("sphere_3d", 3, xyz, flags, h, n, m, alpha, _hv_default(3, alpha), chat, 0,
+                 lo=(-R, -R, -R), hi=(R, R, R))
+    wall = flags != 0
+    nrm = np.zeros((w.N, 3))
+    nrm[wall] = xyz[wall] / np.sqrt((xyz[wall] ** 2).sum(axis=1))[:, None]
+    w.normals = nrm
+    E0, H0, om = _fields.sphere_mode(xyz, 0.0, -0.5 * w.dt, R=R)
+    w.E0, w.H0 = E0, H0
+    w.steps = int(round(periods * 2 * math.pi / om / w.dt))
+    w.meta.update(R=R, omega=om, h_mean=hm)
+    return w
+
+
 REGISTRY = {
     "tm_cavity_2d": tm_cavity_2d,
     "pulse_2d": pulse_2d,
@@ -299,6 +316,7 @@ REGISTRY = {
     "te_cavity_2d": te_cavity_2d,
     "te01_disk": te01_disk,
     "coax_2d": coax_2d,
+    "sphere_3d": sphere_3d,
 }
 
 

@@ -180,6 +180,32 @@ def coax_mode(xyz, t_e, t_h, pol="TM", a=0.5, b=1.0, eps0=1.0, mu0=1.0):
     return np.stack([amp * st, -amp * ct], axis=1), (Z * math.cos(om * t_h))[:, None], om
 
 
+def sphere_mode(xyz, t_e, t_h, R=1.0, eps0=1.0, mu0=1.0):
+    """Lowest azimuthal mode of the PEC sphere |x| <= R (3D).
+
+    E = g(r) (-y, x, 0) cos(omega t) with g(r) = j1(k r) / r, k R the first
+    zero of the spherical Bessel function j1 (E is tangential and vanishes on
+    the wall); Faraday's law gives H = -(curl E) sin(omega t) / (mu0 omega),
+    curl of g (-y, x, 0) = (-x z g'/r, -y z g'/r, 2 g + (x^2 + y^2) g'/r).
+    Returns (E [N, 3] at t_e, H [N, 3] at t_h, omega).
+    """
+    from scipy import optimize, special
+    c0, _ = consts(eps0, mu0)
+    x0 = optimize.brentq(lambda s: special.spherical_jn(1, s), 4.0, 5.0, xtol=1e-15, rtol=1e-15)
+    k = x0 / R
+    om = c0 * k
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    r = np.sqrt(x * x + y * y + z * z)
+    rs = np.where(r > 0, r, 1.0)
+    j1 = special.spherical_jn(1, k * rs)
+    dj1 = special.spherical_jn(1, k * rs, derivative=True)
+    g = np.where(r > 0, j1 / rs, k / 3.0)
+    gr = np.where(r > 0, (k * dj1 * rs - j1) / (rs ** 3), -k ** 3 / 15.0)     # g'(r) / r
+    E = np.stack([-y * g, x * g, np.zeros_like(x)], axis=1) * math.cos(om * t_e)
+    curl = np.stack([-x * z * gr, -y * z * gr, 2.0 * g + (x * x + y * y) * gr], axis=1)
+    return E, -curl * math.sin(om * t_h) / (mu0 * om), om
+
+
 def in_frame(H, theta):
     """Components of the 2D vectors H [N, 2] in the frame with axes
     u_1 = (cos theta, sin theta), u_2 = (-sin theta, cos theta)."""

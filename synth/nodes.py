@@ -269,6 +269,35 @@ def line_seeded_periodic(L=200.0, h=1.0, r_factor=0.794, seed=3, stream=0, round
     return xyz, np.zeros(xyz.shape[0], np.uint8), h, np.arange(nl)
 
 
+def ball_nodes(R=1.0, h=0.1, jitter=0.25, seed=13, stream=0):
+    """Nodes in the ball |x| <= R with a curved wall.
+
+    Wall nodes: round(4 pi R^2 / h^2) points of the Fibonacci lattice on the
+    sphere (flag FACE_XLO); inside, a cubic grid of spacing h centred on the
+    origin with every coordinate moved by U(-jitter h, jitter h) (the node's
+    counter-based stream), kept where |x| < R - h / 2.  Returns (xyz [N, 3],
+    flags [N], h_mean) with h_mean = (4/3 pi R^3 / N)^(1/3).
+    """
+    ns = int(round(4.0 * math.pi * R * R / (h * h)))
+    t = np.arange(ns, dtype=np.float64) + 0.5
+    z = 1.0 - 2.0 * t / ns
+    ph = t * math.pi * (3.0 - math.sqrt(5.0))
+    rxy = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    S = R * np.stack([rxy * np.cos(ph), rxy * np.sin(ph), z], axis=1)
+    m = int(math.ceil(R / h))
+    ax = np.arange(-m, m + 1, dtype=np.float64) * h
+    gz, gy, gx = np.meshgrid(ax, ax, ax, indexing="ij")
+    G = np.stack([gx.reshape(-1), gy.reshape(-1), gz.reshape(-1)], axis=1)
+    ids = np.arange(G.shape[0], dtype=np.uint64)
+    for k in range(3):
+        G[:, k] += rng.uniform_range(seed, stream, ids * np.uint64(3) + np.uint64(k), -jitter * h, jitter * h)
+    G = G[np.sqrt((G * G).sum(axis=1)) < R - 0.5 * h]
+    xyz = np.concatenate([S, G])
+    flags = np.zeros(xyz.shape[0], np.uint8)
+    flags[:ns] = FACE_XLO
+    return xyz, flags, (4.0 / 3.0 * math.pi * R ** 3 / xyz.shape[0]) ** (1.0 / 3.0)
+
+
 def disk_nodes(R=1.0, h=0.02, centre=(0.0, 0.0), r_factor=0.794, seed=9, stream=0, rounds=12, R_in=0.0):
     """Scattered nodes in the disk |x - centre| <= R with a curved wall, or in
     the annulus R_in <= |x - centre| <= R (a conducting cylinder inside).

@@ -143,3 +143,17 @@ def test_wall_normals_validation_on_host():
     bad[inner] = (0.0, 1.0)                                  # normal off the wall
     assert lib.rbffd_set_wall_normals(pl, bad.ctypes.data) == _abi.EINVAL
     lib.rbffd_plan_destroy(pl)
+    # 3D plans take [N][3] normals
+    x3, f3, h3 = nodes.jittered_grid((6, 6, 6), seed=2)
+    x3 = np.ascontiguousarray(x3)
+    p = _params(_abi, dim=3, n=35, n_hv=71)
+    p.hi[2] = 1.0
+    assert lib.rbffd_plan_create(C.byref(p), x3.shape[0], x3.ctypes.data, f3.ctypes.data, 0, None, None,
+                                 C.byref(plan)) == 0
+    n3 = np.zeros((x3.shape[0], 3))
+    w3 = np.nonzero(f3)[0]
+    n3[w3] = (0.0, 0.6, 0.8)
+    assert lib.rbffd_set_wall_normals(plan, n3.ctypes.data) == 0
+    n3[w3[0]] = (0.0, 0.6, 0.7)
+    assert lib.rbffd_set_wall_normals(plan, n3.ctypes.data) == _abi.EINVAL
+    lib.rbffd_plan_destroy(plan)

@@ -443,6 +443,64 @@ def test_te01_circular_cavity_curved_wall():
         assert eE < 1.05 * eEo + 1e-6 and eH < 1.05 * eHo + 1e-6
 
 
+def test_sphere_curved_3d_wall():
+    # a curved 3D wall: the PEC sphere (4858 nodes, 1 1/8 periods, lowest
+    # azimuthal mode), wall nodes keep the normal component of E.  Oracle
+    # weights on the three 3D kernel families, end to end FP64 / FP32 against
+    # the oracle and the closed form; then soft sources on a wall node and an
+    # interior node (the wall node's source is projected) against the oracle
+    _announce("PEC sphere (curved 3D wall)")
+    w = configs.sphere_3d(h=0.1, periods=1.125)
+    oh, oe = osetup.operators(w)
+    Eo, Ho, _, _ = osetup.run_workload(w, oh, oe)
+    Ea, Ha, _ = fields.sphere_mode(w.xyz, w.steps * w.dt, (w.steps - 0.5) * w.dt)
+    eEo, eHo = ostep.linf_errors(Eo, Ho, Ea, Ha)
+    wall = w.flags > 0
+    s = Solver.from_workload(w, precision="f64")
+    _inject(s, oh)
+    for lds in (1, 0, 2):
+        s.set_variant(block=256, xcd=1, lds=lds)
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        e = max(ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho))
+        _announce(f"  injected f64 lds={lds} vs oracle {e:.2e}")
+        assert e < 1e-12
+    # this node set amplifies rounding about 10^3-fold over the run (the FP64
+    # runs above differ from the oracle by ~2.6e-13, i.e. ~10^3 eps64), so the
+    # FP32 bound is 10^3 eps32 rather than the 1e-5 of the other cavities
+    for prec, tol in (("f64", 1e-9), ("f32", 2e-4)):
+        s = Solver.from_workload(w, precision=prec)
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        E, H = s.E_original(st), s.H_original(st)
+        e = max(ostep.rel_l2(E, Eo), ostep.rel_l2(H, Ho))
+        eE, eH = ostep.linf_errors(E, H, Ea, Ha)
+        n = w.normals[wall]
+        tang = np.abs(E[wall] - (E[wall] * n).sum(axis=1)[:, None] * n).max()
+        _announce(f"  {prec} vs oracle {e:.2e}; vs closed form E {eE:.2e} ({eEo:.2e}) H {eH:.2e} ({eHo:.2e}); "
+                  f"tangential E on the wall {tang:.1e}")
+        assert e < tol
+        assert tang <= (1e-15 if prec == "f64" else 1e-6) * np.abs(E).max()
+        assert eE < 1.05 * eEo + 1e-6 and eH < 1.05 * eHo + 1e-6
+    # sources: one on a wall node, one inside
+    T = 60
+    ws = configs.sphere_3d(h=0.1, periods=1.125)
+    ws.steps = T
+    inner = int(np.argmin(np.abs(np.sqrt((ws.xyz ** 2).sum(axis=1)) - 0.5)))
+    ws.src_node = np.array([3, inner])
+    ws.src_amp = np.array([0.7, -0.4])
+    tt = (np.arange(T) + 0.5) * ws.dt
+    ws.src_wave = np.stack([np.exp(-((tt - 0.15) / 0.05) ** 2)] * 2, axis=1)
+    Eo, Ho, _, _ = osetup.run_workload(ws, oh, oe)
+    s = Solver.from_workload(ws, precision="f64")
+    _inject(s, oh)
+    st = s.state(ws.E0, ws.H0)
+    s.run(st, T, src=(ws.src_node, ws.src_amp, ws.src_wave))
+    e = max(ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho))
+    _announce(f"  sources on a wall node and inside, f64 vs oracle {e:.2e}")
+    assert e < 1e-12
+
+
 @pytest.mark.parametrize("pol", ["TM", "TE"])
 def test_coaxial_cavity_inner_conductor(pol):
     # an irregular PEC body: the coaxial cavity 0.5 <= r <= 1 (4014 nodes,

@@ -373,3 +373,24 @@ def test_coaxial_cavity_converges(pol):
     assert eE1 < 4e-3 and eH1 < 4e-3
     assert math.log(eE1 / eE2) / math.log(h1 / h2) >= 1.5
     assert math.log(eH1 / eH2) / math.log(h1 / h2) >= 1.5
+
+
+def test_sphere_cavity_converges():
+    # a curved 3D wall: the PEC sphere with its lowest azimuthal mode
+    # (E = j1(kr)/r (-y, x, 0) cos(omega t), closed form), wall nodes keep the
+    # normal component of E; 1 1/8 periods
+    res = []
+    for h in (0.2, 0.1):
+        w = configs.sphere_3d(h=h, periods=1.125)
+        oh, oe = setup.operators(w)
+        E, H, _, _ = setup.run_workload(w, oh, oe)
+        Ea, Ha, _ = fields.sphere_mode(w.xyz, w.steps * w.dt, (w.steps - 0.5) * w.dt)
+        wall = w.flags > 0
+        n = w.normals[wall]
+        tang = E[wall] - (E[wall] * n).sum(axis=1)[:, None] * n
+        assert np.abs(tang).max() < 1e-15
+        res.append(step.linf_errors(E, H, Ea, Ha) + (w.meta["h_mean"],))
+    (eE1, eH1, h1), (eE2, eH2, h2) = res
+    assert eE2 < 2e-2 and eH2 < 3e-2
+    assert math.log(eE1 / eE2) / math.log(h1 / h2) >= 1.5
+    assert math.log(eH1 / eH2) / math.log(h1 / h2) >= 1.5
