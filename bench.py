@@ -45,19 +45,20 @@ def alg_bytes_half(n, nh, d, sw, sf, fe, fh, which):
 
 
 def time_halves(s, st, reps, torch):
-    """Average duration of each half-update kernel, HIP events on the library's stream."""
+    """Average duration of each half-update kernel: a HIP event pair around
+    every launch on the library's stream, so that host-side gaps between
+    launches are not counted."""
     stream = torch.cuda.current_stream()
     out = []
     for which in (0, 1):
         s.half(st, which)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record(stream)
             s.half(st, which)
-        e1.record(stream)
-        e1.synchronize()
-        out.append(e0.elapsed_time(e1) / reps * 1e-3)
+            e1.record(stream)
+        ev[-1][1].synchronize()
+        out.append(sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps * 1e-3)
     return out
 
 
