@@ -45,20 +45,31 @@ def alg_bytes_half(n, nh, d, sw, sf, fe, fh, which):
 
 
 def time_halves(s, st, reps, torch):
-    """Average duration of each half-update kernel: a HIP event pair around
-    every launch on the library's stream, so that host-side gaps between
-    launches are not counted."""
+    """Average duration of each half-update kernel: reps back-to-back launches
+    between one HIP event pair on the library's stream.  The field structs are
+    built once and the ABI call is made directly, so the host enqueues far
+    faster than the kernels run and no gaps enter the average; consecutive
+    launches alternate the two buffers of each pair, as the step loop does,
+    so that no launch rewrites the buffer its predecessor has just written."""
     stream = torch.cuda.current_stream()
+    fa = st.struct()
+    fb = st.struct()
+    fb.cur = 1 - fa.cur
+    sp = s.stream()
     out = []
     for which in (0, 1):
         s.half(st, which)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-        for e0, e1 in ev:
-            e0.record(stream)
-            s.half(st, which)
-            e1.record(stream)
-        ev[-1][1].synchronize()
-        out.append(sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps * 1e-3)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        rc = 0
+        e0.record(stream)
+        for r in range(reps):
+            rc |= s.lib.rbffd_half(s.plan, ctypes.byref(fa if r % 2 == 0 else fb), which, sp)
+        e1.record(stream)
+        e1.synchronize()
+        if rc:
+            raise RuntimeError(f"rbffd_half failed ({rc})")
+        out.append(e0.elapsed_time(e1) / reps * 1e-3)
     return out
 
 
