@@ -54,7 +54,8 @@ extern "C" {
  *   Ex <- Ex + kappa (D^dy Hz_new + gamma D^hv Ex)
  *   Ey <- Ey + kappa (-D^dx Hz_new + gamma D^hv Ey)
  * (Hz at half steps); a wall flagged as normal to x zeroes Ey, one normal to
- * y zeroes Ex (axis-aligned walls).  Sources, receivers, the K-field batch,
+ * y zeroes Ex (axis-aligned walls; curved walls take per-node normals, see
+ * rbffd_set_wall_normals).  Sources, receivers, the K-field batch,
  * the adjoint and the two-set variant are TMz only. */
 #define RBFFD_POL_TM 0
 #define RBFFD_POL_TE 1
