@@ -82,9 +82,8 @@ struct NodeSet {
     double* xyz = nullptr;        // [N][dim] internal order
     uint8_t* emask = nullptr;     // [N] bit c = E component c free (E set only);
                                   // bit 3 = curved wall with a normal in nrm
-    std::vector<double> nrm_host; // [N][2] unit wall normals, original order (TEz)
-    double* nrm_in = nullptr;     // [N][2] original order (TEz PEC plans only)
-    double* nrm = nullptr;        // [N][2] internal order
+    std::vector<double> nrm_host; // [N][dim] unit wall normals, original order
+    double* nrm = nullptr;        // [N][dim] internal order (see has_wall_normals)
     double h = 0;
 };
 
@@ -125,6 +124,12 @@ struct rbffd_plan {
     int ex_m[RBFFD_MAX_MONO][3];   // monomial exponents (curl)
     int ex_h[RBFFD_MAX_MONO][3];   // monomial exponents (hv)
 };
+
+// Plans whose PEC walls may be curved keep per-node wall normals: where E is
+// a vector (TEz, 3D) and the walls are PEC.
+inline bool has_wall_normals(const rbffd_plan* p) {
+    return p->p.bc == RBFFD_BC_PEC && (p->p.pol == RBFFD_POL_TE || p->dim == 3);
+}
 
 // ---- run workspace: FP64 reduction partials, the device step counter -------
 constexpr int RED_BLOCKS = 1024;

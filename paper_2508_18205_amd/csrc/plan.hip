@@ -79,7 +79,6 @@ void layout_set(Bump& b, NodeSet& S, int dim, bool is_e, bool normals) {
     S.inv = b.take<int32_t>(S.N);
     S.xyz = b.take<double>(S.N * dim);
     S.emask = is_e ? b.take<uint8_t>(S.N) : nullptr;
-    S.nrm_in = normals ? b.take<double>(S.N * dim) : nullptr;
     S.nrm = normals ? b.take<double>(S.N * dim) : nullptr;
 }
 
@@ -130,9 +129,7 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int K, bool adjoint) {
 int64_t layout_arena(rbffd_plan* p, char* base, int64_t* ws, int64_t* adj_ws) {
     Bump b{base};
     const int wb = weight_elem_bytes(p->p.wdtype);
-    // curved walls need per-node normals where E is a vector: TEz and 3D
-    const bool curved = p->p.bc == RBFFD_BC_PEC && (p->p.pol == RBFFD_POL_TE || p->dim == 3);
-    layout_set(b, p->E, p->dim, true, curved);
+    layout_set(b, p->E, p->dim, true, has_wall_normals(p));
     if (!p->collocated) layout_set(b, p->H, p->dim, false, false);
     layout_block(b, p->opH, p->dim, wb, p->K, p->p.adjoint != 0);
     if (!p->collocated) layout_block(b, p->opE, p->dim, wb, p->K, false);

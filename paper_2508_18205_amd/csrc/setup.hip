@@ -936,6 +936,7 @@ int64_t setup_ws_bytes(const rbffd_plan* p) {
         w.take<int32_t>(p->E.N * std::max(p->nh, 1));
     }
     w.take<int32_t>(64);   // status
+    if (has_wall_normals(p)) w.take<double>(p->E.N * p->dim);   // normals, original order
     int64_t need = w.off;
     if (p->collocated) {
         WS t{nullptr};
@@ -991,13 +992,14 @@ int setup_nodes_and_stencils(rbffd_plan* p, void* wsp, hipStream_t st) {
         kEh = w.take<int32_t>(p->E.N * std::max(p->nh, 1));
     }
     int32_t* status = w.take<int32_t>(64);
+    double* nrm_in = has_wall_normals(p) ? w.take<double>(p->E.N * d) : nullptr;   // original order
     // upload node data
     HIPCHK(p, hipMemcpyAsync(p->E.xyz_in, p->E.xyz_host.data(), p->E.N * d * 8, hipMemcpyHostToDevice, st));
     HIPCHK(p, hipMemcpyAsync(p->E.flags_in, p->E.flags_host.data(), p->E.N, hipMemcpyHostToDevice, st));
-    if (p->E.nrm_in) {
+    if (nrm_in) {
         const size_t nb = (size_t)p->E.N * d * 8;
-        if (p->E.nrm_host.empty()) HIPCHK(p, hipMemsetAsync(p->E.nrm_in, 0, nb, st));
-        else HIPCHK(p, hipMemcpyAsync(p->E.nrm_in, p->E.nrm_host.data(), nb, hipMemcpyHostToDevice, st));
+        if (p->E.nrm_host.empty()) HIPCHK(p, hipMemsetAsync(nrm_in, 0, nb, st));
+        else HIPCHK(p, hipMemcpyAsync(nrm_in, p->E.nrm_host.data(), nb, hipMemcpyHostToDevice, st));
     }
     int rc = build_search(p, p->E, se, st);
     if (rc) return rc;
@@ -1033,7 +1035,8 @@ int setup_nodes_and_stencils(rbffd_plan* p, void* wsp, hipStream_t st) {
         }
         hipLaunchKernelGGL(k_inverse, dim3(blocks(S.N)), dim3(256), 0, st, S.perm, S.N, S.inv);
         hipLaunchKernelGGL(k_internal_nodes, dim3(blocks(S.N)), dim3(256), 0, st, S.xyz_in, S.flags_in, S.perm, S.N, d,
-                           S.xyz, S.emask, (int)per, (int)(p->p.pol == RBFFD_POL_TE), S.nrm_in, S.nrm);
+                           S.xyz, S.emask, (int)per, (int)(p->p.pol == RBFFD_POL_TE),
+                           &S == &p->E ? nrm_in : nullptr, S.nrm);
         return RBFFD_OK;
     };
     if (p->p.reorder == RBFFD_ORDER_RCM && !p->collocated)
