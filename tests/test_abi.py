@@ -83,6 +83,10 @@ def test_plan_validation_and_sizes_on_host():
         rc = lib.rbffd_plan_create(C.byref(p), xyz.shape[0], xyz.ctypes.data, flags.ctypes.data, 0, None, None,
                                    C.byref(plan))
         assert rc in (_abi.EINVAL, _abi.ESIZE, _abi.ENOTSUP), bad
+    # empty node set
+    p = _params(_abi)
+    assert lib.rbffd_plan_create(C.byref(p), 0, xyz.ctypes.data, flags.ctypes.data, 0, None, None,
+                                 C.byref(plan)) == _abi.ESIZE
     assert lib.rbffd_strerror(_abi.ESINGULAR) == b"singular local weight system"
     # TEz polarisation: (Ex, Ey) and Hz per node; collocated 2D, K = 1 only
     p = _params(_abi, pol=1)

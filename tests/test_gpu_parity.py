@@ -618,3 +618,20 @@ def test_leapfrog_time_reversal_on_the_gpu(case):
         eH = np.abs(H + H1).max() / np.abs(H1).max()
         _announce(f"  lds={lds}: E {eE:.2e} H {eH:.2e}")
         assert eE < 1e-10 and eH < 1e-10
+
+
+def test_zero_steps_are_no_ops_and_negative_counts_are_refused():
+    # degenerate calls: 0 steps and a run of T = 0 leave the state untouched
+    # (bit for bit); a negative step count is an error, not a launch
+    from paper_2508_18205_amd._abi import RbffdError
+    _announce("zero-step calls")
+    w = configs.tm_cavity_2d(scale=0.3)
+    s = Solver.from_workload(w, precision="f64")
+    st = s.state(w.E0, w.H0)
+    E0, H0 = s.E_original(st).copy(), s.H_original(st).copy()
+    s.step(st, 0)
+    s.run(st, 0, use_graph=True)
+    assert (s.E_original(st) == E0).all() and (s.H_original(st) == H0).all()
+    with pytest.raises(RbffdError):
+        s.step(st, -1)
+    assert (s.E_original(st) == E0).all()
