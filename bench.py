@@ -588,8 +588,10 @@ def main():
         for key, make, exact in (("tm01_disk", configs.tm01_disk, _fields.tm01_disk),
                                  ("te01_disk", configs.te01_disk, _fields.te01_disk),
                                  ("coax_tm01", coax["TM"][0], coax["TM"][1]),
-                                 ("coax_te01", coax["TE"][0], coax["TE"][1])):
-            wk = make(h=0.0025)
+                                 ("coax_te01", coax["TE"][0], coax["TE"][1]),
+                                 ("sphere_3d", configs.sphere_3d, _fields.sphere_mode)):
+            # the 3D sphere (curved 3D wall) at h = 0.02: ~0.55M nodes
+            wk = make(h=0.02) if key == "sphere_3d" else make(h=0.0025)
             sk, tk = setup_w(wk, "f32")
             ak = sk.state(wk.E0, wk.H0)
             if not args.no_tune:
