@@ -153,8 +153,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this "
-              f"build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library has no multi-GPU path "
+              f"(one process drives one GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
