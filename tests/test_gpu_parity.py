@@ -635,3 +635,25 @@ def test_zero_steps_are_no_ops_and_negative_counts_are_refused():
     with pytest.raises(RbffdError):
         s.step(st, -1)
     assert (s.E_original(st) == E0).all()
+
+
+def test_graph_replays_with_eager_work_between_them():
+    # three graph-replayed runs with eager steps and synchronisations between
+    # them match the all-eager path bit for bit after every run (fields and
+    # the energy series), in FP64 and FP32
+    _announce("graph replays interleaved with eager work")
+    w = configs.tm_cavity_2d(scale=0.6, chat=1e-3)
+    for prec in ("f64", "f32"):
+        s = Solver.from_workload(w, precision=prec)
+        sg = s.state(w.E0, w.H0)
+        se = s.state(w.E0, w.H0)
+        for rep in range(3):
+            og = s.run(sg, 40, energy_every=10, use_graph=True)
+            torch.cuda.synchronize()
+            s.step(sg, 3)
+            oe = s.run(se, 40, energy_every=10, use_graph=False)
+            s.step(se, 3)
+            torch.cuda.synchronize()
+            assert (s.E_original(sg) == s.E_original(se)).all(), (prec, rep)
+            assert (s.H_original(sg) == s.H_original(se)).all(), (prec, rep)
+            assert (og["energy"] == oe["energy"]).all(), (prec, rep)
