@@ -588,6 +588,16 @@ def test_te_polarisation_cavity_and_periodic():
     e = max(ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho))
     _announce(f"  periodic f64 vs oracle {e:.2e}")
     assert e < 1e-9
+    # the same periodic set with the derivatives taken in a turned frame
+    wp.frame_angle = 0.4
+    ohp, oep = osetup.operators(wp)
+    Eo, Ho, _, _ = osetup.run_workload(wp, ohp, oep)
+    s = Solver.from_workload(wp, precision="f64")
+    st = s.state(wp.E0, wp.H0)
+    s.step(st, wp.steps)
+    e = max(ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho))
+    _announce(f"  periodic, turned frame, f64 vs oracle {e:.2e}")
+    assert e < 1e-9
 
 
 @pytest.mark.parametrize("case", ["2d", "3d"])
