@@ -316,6 +316,77 @@ __device__ __forceinline__ double dmono_at0(const int8_t* e, int d, const double
     return deg == 1 ? u[ax] : 0.0;
 }
 
+// Entry (i, j) of the augmented local system [A~ | B] (eq. 9 with the
+// eq. 13 / eq. 15 / Delta^alpha right-hand sides) from the scaled offsets xi
+// [n][3] and the stencil scale sc.
+__device__ __forceinline__ double system_entry(const WArgs& a, const double* xi, double sc, int i, int j) {
+    const int n = a.n, R = n + a.M, d = a.d;
+    double v = 0.0;
+    if (j < R) {
+        if (i < n && j < n) {
+            double r2 = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double t = xi[i * 3 + k] - xi[j * 3 + k];
+                r2 += t * t;
+            }
+            v = phs(sqrt(r2), a.phs_k);
+        } else if (i < n && j >= n) {
+            v = mono(xi + i * 3, a.ex[j - n], d);
+        } else if (i >= n && j < n) {
+            v = mono(xi + j * 3, a.ex[i - n], d);
+        }
+    } else {
+        const int col = j - R;   // right-hand side index (derivative direction)
+        const double* u = a.fu[col];
+        if (a.kind == W_FD) {
+            if (i < n) {
+                double r2 = 0.0, xu = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    r2 += xi[i * 3 + k] * xi[i * 3 + k];
+                    xu += xi[i * 3 + k] * u[k];
+                }
+                const double r = sqrt(r2);
+                // u . grad |x - xi_i|^k at x = 0 = -k r^(k-2) (xi_i . u)
+                v = -(double)a.phs_k * phs(r, a.phs_k - 2) * xu;
+            } else {
+                v = dmono_at0(a.ex[i - n], d, u);
+            }
+        } else if (a.kind == W_VFD) {
+            // central virtual difference: (-1/2 f(-delta u) + 1/2 f(+delta u)) / delta
+            const double dl = a.vdelta / sc;
+            double xm[3] = {0, 0, 0}, xp[3] = {0, 0, 0};
+            for (int k = 0; k < d; ++k) {
+                xm[k] = -dl * u[k];
+                xp[k] = dl * u[k];
+            }
+            double fm, fp;
+            if (i < n) {
+                double r2m = 0.0, r2p = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    const double tm = xm[k] - xi[i * 3 + k], tp = xp[k] - xi[i * 3 + k];
+                    r2m += tm * tm;
+                    r2p += tp * tp;
+                }
+                fm = phs(sqrt(r2m), a.phs_k);
+                fp = phs(sqrt(r2p), a.phs_k);
+            } else {
+                fm = mono(xm, a.ex[i - n], d);
+                fp = mono(xp, a.ex[i - n], d);
+            }
+            v = (-0.5 * fm + 0.5 * fp) / dl;
+        } else {
+            if (i < n) {
+                double r2 = 0.0;
+                for (int k = 0; k < d; ++k) r2 += xi[i * 3 + k] * xi[i * 3 + k];
+                v = a.hv_C * sqrt(r2);
+            } else {
+                v = a.hv_poly[i - n];
+            }
+        }
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(1024) void k_weights(WArgs a) {
     extern __shared__ double lds[];
     const int64_t c = a.c0 + blockIdx.x;
@@ -369,69 +440,7 @@ __global__ __launch_bounds__(1024) void k_weights(WArgs a) {
     // 2. assemble [A~ | B]
     for (int e = tid; e < R * lda; e += nt) {
         const int i = e / lda, j = e % lda;
-        double v = 0.0;
-        if (j < R) {
-            if (i < n && j < n) {
-                double r2 = 0.0;
-                for (int k = 0; k < d; ++k) {
-                    const double t = xi[i * 3 + k] - xi[j * 3 + k];
-                    r2 += t * t;
-                }
-                v = phs(sqrt(r2), a.phs_k);
-            } else if (i < n && j >= n) {
-                v = mono(xi + i * 3, a.ex[j - n], d);
-            } else if (i >= n && j < n) {
-                v = mono(xi + j * 3, a.ex[i - n], d);
-            }
-        } else {
-            const int col = j - R;   // right-hand side index (derivative direction)
-            const double* u = a.fu[col];
-            if (a.kind == W_FD) {
-                if (i < n) {
-                    double r2 = 0.0, xu = 0.0;
-                    for (int k = 0; k < d; ++k) {
-                        r2 += xi[i * 3 + k] * xi[i * 3 + k];
-                        xu += xi[i * 3 + k] * u[k];
-                    }
-                    const double r = sqrt(r2);
-                    // u . grad |x - xi_i|^k at x = 0 = -k r^(k-2) (xi_i . u)
-                    v = -(double)a.phs_k * phs(r, a.phs_k - 2) * xu;
-                } else {
-                    v = dmono_at0(a.ex[i - n], d, u);
-                }
-            } else if (a.kind == W_VFD) {
-                // central virtual difference: (-1/2 f(-delta u) + 1/2 f(+delta u)) / delta
-                const double dl = a.vdelta / sc;
-                double xm[3] = {0, 0, 0}, xp[3] = {0, 0, 0};
-                for (int k = 0; k < d; ++k) {
-                    xm[k] = -dl * u[k];
-                    xp[k] = dl * u[k];
-                }
-                double fm, fp;
-                if (i < n) {
-                    double r2m = 0.0, r2p = 0.0;
-                    for (int k = 0; k < d; ++k) {
-                        const double tm = xm[k] - xi[i * 3 + k], tp = xp[k] - xi[i * 3 + k];
-                        r2m += tm * tm;
-                        r2p += tp * tp;
-                    }
-                    fm = phs(sqrt(r2m), a.phs_k);
-                    fp = phs(sqrt(r2p), a.phs_k);
-                } else {
-                    fm = mono(xm, a.ex[i - n], d);
-                    fp = mono(xp, a.ex[i - n], d);
-                }
-                v = (-0.5 * fm + 0.5 * fp) / dl;
-            } else {
-                if (i < n) {
-                    double r2 = 0.0;
-                    for (int k = 0; k < d; ++k) r2 += xi[i * 3 + k] * xi[i * 3 + k];
-                    v = a.hv_C * sqrt(r2);
-                } else {
-                    v = a.hv_poly[i - n];
-                }
-            }
-        }
+        const double v = system_entry(a, xi, sc, i, j);
         Am[i * lda + j] = v;
     }
     __syncthreads();
@@ -506,6 +515,213 @@ __global__ __launch_bounds__(1024) void k_weights(WArgs a) {
     for (int e = tid; e < a.nrhs * n; e += nt) {
         const int q = e / n, j = e % n;
         a.out[c * a.nrhs * n + e] = Am[prm[j] * lda + R + q] / us;
+    }
+}
+
+// Register-resident variant for systems with R + nrhs <= 16 B (B <= 7): a
+// 256-thread workgroup per system seen as a 16 x 16 grid; thread (tr, tc)
+// holds the entries (tr + 16 a, tc + 16 b), a, b < B, of [A~ | B] in
+// registers.  Gauss-Jordan elimination with partial pivoting (largest |value|
+// among the rows not yet used as pivots, ties to the lower row): one barrier
+// after the pivot candidates, one after the pivot row and the multipliers are
+// published in LDS, per column; no back substitution.  The LDS footprint is a
+// few KB, so several systems share a CU (the LDS-resident kernel holds one
+// 106-unknown system per CU).
+constexpr int WREG_T = 16, WREG_BMAX = 7, WREG_MAX = WREG_T * WREG_BMAX;
+
+// Column b / row r of the register block for an index that is the same in
+// every thread: a switch on it compiles to scalar branches, and each case
+// reads the registers with compile-time indices.
+template <int B>
+__device__ __forceinline__ void reg_col(const double (&m)[B][B], int b, double (&out)[B]) {
+    switch (b) {
+#define WREG_COL(C)                                                            \
+    case C:                                                                    \
+        _Pragma("unroll") for (int r = 0; r < B; ++r) out[r] = m[r][C < B ? C : B - 1]; \
+        break;
+        WREG_COL(0) WREG_COL(1) WREG_COL(2) WREG_COL(3) WREG_COL(4) WREG_COL(5)
+#undef WREG_COL
+        default:
+            _Pragma("unroll") for (int r = 0; r < B; ++r) out[r] = m[r][B - 1];
+    }
+}
+template <int B>
+__device__ __forceinline__ void reg_row(const double (&m)[B][B], int a, double (&out)[B]) {
+    switch (a) {
+#define WREG_ROW(A)                                                            \
+    case A:                                                                    \
+        _Pragma("unroll") for (int q = 0; q < B; ++q) out[q] = m[A < B ? A : B - 1][q]; \
+        break;
+        WREG_ROW(0) WREG_ROW(1) WREG_ROW(2) WREG_ROW(3) WREG_ROW(4) WREG_ROW(5)
+#undef WREG_ROW
+        default:
+            _Pragma("unroll") for (int q = 0; q < B; ++q) out[q] = m[B - 1][q];
+    }
+}
+
+template <int WREG_B>
+__global__ __launch_bounds__(256, 3) void k_wreg(WArgs a) {
+    __shared__ double xi[WREG_MAX * 3];
+    __shared__ double band[WREG_T * WREG_MAX];   // one 16-row band during assembly
+    __shared__ double prow[WREG_MAX], mcol[WREG_MAX], dpiv[WREG_MAX];
+    __shared__ double cval[WREG_T];
+    __shared__ int cidx[WREG_T];
+    __shared__ int kof[WREG_MAX];                // column pivoted on row i, -1 before
+    __shared__ double s_scale;
+    const int64_t c = a.c0 + blockIdx.x;
+    if (c >= a.Nt) return;                       // uniform over the workgroup
+    const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+    const int n = a.n, R = n + a.M, d = a.d;
+    const int lda = R + a.nrhs;
+
+    // 1. offsets from the centre and the stencil radius (as k_weights)
+    const double* xc = a.txyz + c * d;
+    const int32_t* row = a.st + c * a.st_stride;
+    for (int j = tid; j < n; j += 256) {
+        const double* xj = a.sxyz + (int64_t)row[j] * d;
+        for (int k = 0; k < 3; ++k) xi[j * 3 + k] = 0.0;
+        for (int k = 0; k < d; ++k) {
+            double dk = xj[k] - xc[k];
+            if (a.periodic) {
+                const double L = a.period[k];
+                if (dk > 0.5 * L) dk -= L;
+                if (dk < -0.5 * L) dk += L;
+            }
+            xi[j * 3 + k] = dk;
+        }
+    }
+    for (int i = tid; i < WREG_MAX; i += 256) {
+        kof[i] = -1;
+        prow[i] = 0.0;
+        mcol[i] = 0.0;
+    }
+    if (tid == 0 && a.check_self && row[0] != (int32_t)c) atomicAdd(&a.status[1], 1);
+    __syncthreads();
+    if (tid < 64) {
+        double mx = 0.0;
+        for (int j = tid; j < n; j += 64) {
+            double r2 = 0.0;
+            for (int k = 0; k < d; ++k) r2 += xi[j * 3 + k] * xi[j * 3 + k];
+            mx = fmax(mx, sqrt(r2));
+        }
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+        if (tid == 0) s_scale = mx;
+    }
+    __syncthreads();
+    const double sc = s_scale;
+    for (int j = tid; j < n * 3; j += 256) xi[j] = xi[j] / sc;
+    __syncthreads();
+
+    // 2. assemble band by band through LDS into the registers
+    double m[WREG_B][WREG_B];
+#pragma unroll
+    for (int ra = 0; ra < WREG_B; ++ra) {
+        for (int e = tid; e < WREG_T * lda; e += 256) {
+            const int i = WREG_T * ra + e / lda, j = e % lda;
+            band[e] = i < R ? system_entry(a, xi, sc, i, j) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int cb = 0; cb < WREG_B; ++cb) {
+            const int j = tc + WREG_T * cb;
+            m[ra][cb] = j < lda ? band[tr * lda + j] : 0.0;
+        }
+        __syncthreads();
+    }
+
+    // 3. Gauss-Jordan elimination.  The padding rows (i >= R) and columns
+    // (j >= lda) hold zeros and stay zero, so every step below is written
+    // without per-element branches: predicates become selects and LDS reads
+    // are unconditional (all arrays have WREG_MAX entries).
+    bool bad = false;
+    for (int k = 0; k < R; ++k) {
+        const int bk = k >> 4, ck = k & 15;
+        if (tc == ck) {
+            double colk[WREG_B];
+            reg_col(m, bk, colk);
+            double best = -1.0, bval = 0.0;
+            int bi = R;
+#pragma unroll
+            for (int ra = 0; ra < WREG_B; ++ra) {
+                const int i = tr + WREG_T * ra;
+                const double v = colk[ra];
+                const bool take = (i < R) & (kof[i] < 0) & (fabs(v) > best);
+                best = take ? fabs(v) : best;
+                bval = take ? v : bval;
+                bi = take ? i : bi;
+            }
+            cval[tr] = bval;
+            cidx[tr] = bi;
+        }
+        __syncthreads();
+        double pbest = -1.0, pval = 0.0;
+        int p = R;
+#pragma unroll
+        for (int t = 0; t < WREG_T; ++t) {
+            const int ii = cidx[t];
+            const double vv = cval[t], av = fabs(vv);
+            const bool take = (ii < R) & ((av > pbest) | ((av == pbest) & (ii < p)));
+            pbest = take ? av : pbest;
+            pval = take ? vv : pval;
+            p = take ? ii : p;
+        }
+        if (!(pbest > 0.0)) {                    // the same decision in every thread
+            bad = true;
+            break;
+        }
+        if (tr == (p & 15)) {
+            double rowp[WREG_B];
+            reg_row(m, p >> 4, rowp);
+#pragma unroll
+            for (int cb = 0; cb < WREG_B; ++cb) prow[tc + WREG_T * cb] = rowp[cb];
+        }
+        if (tc == ck) {
+            double colk[WREG_B];
+            reg_col(m, bk, colk);
+            const double rp = 1.0 / pval;
+#pragma unroll
+            for (int ra = 0; ra < WREG_B; ++ra) {
+                const int i = tr + WREG_T * ra;
+                mcol[i] = (i == p) ? 0.0 : colk[ra] * rp;
+            }
+        }
+        if (tid == 0) {
+            kof[p] = k;
+            dpiv[k] = pval;
+        }
+        __syncthreads();
+        double pj[WREG_B];
+#pragma unroll
+        for (int cb = 0; cb < WREG_B; ++cb) {
+            const int j = tc + WREG_T * cb;
+            pj[cb] = (j > k) ? prow[j] : 0.0;
+        }
+#pragma unroll
+        for (int ra = 0; ra < WREG_B; ++ra) {
+            const double mi = mcol[tr + WREG_T * ra];
+#pragma unroll
+            for (int cb = 0; cb < WREG_B; ++cb) m[ra][cb] -= mi * pj[cb];
+        }
+    }
+    if (bad) {
+        if (tid == 0) atomicMin(&a.status[0], (int32_t)c);
+        for (int e = tid; e < a.nrhs * n; e += 256) a.out[c * a.nrhs * n + e] = 0.0;
+        return;
+    }
+    // 4. unknown k sits in the row pivoted at column k; unscale and store the
+    // first n entries of every right-hand side
+    const double us = ipow(sc, a.upow);
+#pragma unroll
+    for (int ra = 0; ra < WREG_B; ++ra) {
+        const int i = tr + WREG_T * ra;
+        if (i >= R) continue;
+        const int k = kof[i];
+        if (k >= n) continue;
+#pragma unroll
+        for (int cb = 0; cb < WREG_B; ++cb) {
+            const int j = tc + WREG_T * cb;
+            if (j >= R && j < lda) a.out[c * a.nrhs * n + (int64_t)(j - R) * n + k] = m[ra][cb] / dpiv[k] / us;
+        }
     }
 }
 
@@ -1127,6 +1343,22 @@ static int launch_weights(rbffd_plan* p, const OpBlock& o, const NodeSet& T, con
         a.check_self = 1;
     }
     const int R = a.n + a.M;
+    constexpr int64_t chunk = (int64_t)1 << 21;   // a dispatch counts work-items in 32 bits
+    if (R + a.nrhs <= WREG_MAX) {
+        // the system fits the register-resident solver (every configured
+        // workload), with the smallest register block that holds it
+        const int blk = (R + a.nrhs + WREG_T - 1) / WREG_T;
+        for (int64_t c0 = 0; c0 < o.Nt; c0 += chunk) {
+            a.c0 = c0;
+            const int64_t nb = std::min<int64_t>(chunk, o.Nt - c0);
+            if (blk <= 3) hipLaunchKernelGGL(k_wreg<3>, dim3((unsigned)nb), dim3(256), 0, st, a);
+            else if (blk <= 4) hipLaunchKernelGGL(k_wreg<4>, dim3((unsigned)nb), dim3(256), 0, st, a);
+            else if (blk <= 6) hipLaunchKernelGGL(k_wreg<6>, dim3((unsigned)nb), dim3(256), 0, st, a);
+            else hipLaunchKernelGGL(k_wreg<7>, dim3((unsigned)nb), dim3(256), 0, st, a);
+            HIPCHK(p, hipGetLastError());
+        }
+        return RBFFD_OK;
+    }
     const size_t lds = (size_t)(R * (R + a.nrhs) + a.n * 3 + R) * 8;
     int dev = 0, max_lds = 65536;
     HIPCHK(p, hipGetDevice(&dev));
@@ -1135,10 +1367,9 @@ static int launch_weights(rbffd_plan* p, const OpBlock& o, const NodeSet& T, con
         return set_err(p, RBFFD_ESIZE, "local system of " + std::to_string(R) + " unknowns needs " +
                                            std::to_string(lds) + " B of LDS; the device allows " +
                                            std::to_string(max_lds));
-    // 16 wavefronts per system: the elimination steps are chains of LDS
-    // round trips, so more wavefronts hide more of their latency.  A dispatch
-    // counts its work-items in 32 bits, so at most 2^21 systems per launch.
-    constexpr int64_t chunk = (int64_t)1 << 21;
+    // larger systems: 16 wavefronts per system with the matrix in LDS; the
+    // elimination steps are chains of LDS round trips, so more wavefronts hide
+    // more of their latency (at most 2^21 systems per launch, as above)
     for (int64_t c0 = 0; c0 < o.Nt; c0 += chunk) {
         a.c0 = c0;
         const int64_t nb = std::min<int64_t>(chunk, o.Nt - c0);
