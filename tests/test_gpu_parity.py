@@ -78,6 +78,21 @@ def test_order_and_stencils_bit_exact(case):
     assert (st == ref).all()
 
 
+def test_weights_of_systems_beyond_the_register_solver():
+    # a curl stencil of n = 100 with m = 4 (115 unknowns + 2 right-hand sides)
+    # exceeds the register-resident solver and takes the LDS-resident one;
+    # the HV system (31 + 15 unknowns) stays on the register solver
+    _announce("weights: large local systems (LDS solver)")
+    w = configs.tm_cavity_2d(n_side=21, n=100, m=4)
+    s = Solver.from_workload(w, precision="f64")
+    oh, _ = osetup.operators(w)
+    p = s.perm
+    ec = _weight_err(s.weights(_abi.OP_CURL_H), oh["curl_w"][p])
+    eh = _weight_err(s.weights(_abi.OP_HV_H), oh["hv_w"][p])
+    _announce(f"  max rel weight err curl {ec.max():.2e} hv {eh.max():.2e}")
+    assert ec.max() < 1e-9 and eh.max() < 1e-9
+
+
 @pytest.mark.parametrize("mode", ["FD", "VFD"])
 def test_weights_match_oracle_2d(mode):
     _announce(f"weights 2D {mode}")
