@@ -636,11 +636,11 @@ __global__ __launch_bounds__(256, 3) void k_wreg(WArgs a) {
     bool bad = false;
     for (int k = 0; k < R; ++k) {
         const int bk = k >> 4, ck = k & 15;
+        double best = -1.0, bval = 0.0;
+        int bi = R;
         if (tc == ck) {
             double colk[WREG_B];
             reg_col(m, bk, colk);
-            double best = -1.0, bval = 0.0;
-            int bi = R;
 #pragma unroll
             for (int ra = 0; ra < WREG_B; ++ra) {
                 const int i = tr + WREG_T * ra;
@@ -650,14 +650,27 @@ __global__ __launch_bounds__(256, 3) void k_wreg(WArgs a) {
                 bval = take ? v : bval;
                 bi = take ? i : bi;
             }
-            cval[tr] = bval;
-            cidx[tr] = bi;
+        }
+        // the four thread rows of a wavefront hold lanes tc, tc + 16, tc + 32,
+        // tc + 48: reduce over them, one candidate per wavefront into LDS
+#pragma unroll
+        for (int off = 16; off <= 32; off <<= 1) {
+            const double ob = __shfl_xor(best, off, 64), ov = __shfl_xor(bval, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            const bool take = (ob > best) | ((ob == best) & (oi < bi));
+            best = take ? ob : best;
+            bval = take ? ov : bval;
+            bi = take ? oi : bi;
+        }
+        if ((tid & 63) == ck) {
+            cval[tid >> 6] = bval;
+            cidx[tid >> 6] = bi;
         }
         __syncthreads();
         double pbest = -1.0, pval = 0.0;
         int p = R;
 #pragma unroll
-        for (int t = 0; t < WREG_T; ++t) {
+        for (int t = 0; t < 256 / 64; ++t) {
             const int ii = cidx[t];
             const double vv = cval[t], av = fabs(vv);
             const bool take = (ii < R) & ((av > pbest) | ((av == pbest) & (ii < p)));
