@@ -125,26 +125,60 @@ __device__ __forceinline__ double sq_dist(const double* a, const double* b, int 
     return acc;
 }
 
+// The k smallest (d2, id) pairs seen so far, as a binary max-heap (the root is
+// the current k-th nearest); finish() heap-sorts them into ascending order.
+// Pairs are totally ordered (ids are distinct), so the result is the same
+// list an insertion sort would give.
 template <int KMAX>
 struct TopK {
     double d2[KMAX];
     int32_t id[KMAX];
     int cnt = 0;
-    __device__ __forceinline__ void push(double dd, int32_t o, int k) {
-        if (cnt == k) {
-            const double wd = d2[k - 1];
-            if (!(dd < wd || (dd == wd && o < id[k - 1]))) return;
-        } else {
-            ++cnt;
-        }
-        int pos = cnt - 1;
-        while (pos > 0 && (dd < d2[pos - 1] || (dd == d2[pos - 1] && o < id[pos - 1]))) {
-            d2[pos] = d2[pos - 1];
-            id[pos] = id[pos - 1];
-            --pos;
+    __device__ static __forceinline__ bool gt(double a, int32_t ia, double b, int32_t ib) {
+        return a > b || (a == b && ia > ib);
+    }
+    __device__ __forceinline__ void sift_down(double dd, int32_t o, int n) {
+        int pos = 0;
+        for (;;) {
+            const int l = 2 * pos + 1;
+            if (l >= n) break;
+            const int r = l + 1;
+            const int c = (r < n && gt(d2[r], id[r], d2[l], id[l])) ? r : l;
+            if (!gt(d2[c], id[c], dd, o)) break;
+            d2[pos] = d2[c];
+            id[pos] = id[c];
+            pos = c;
         }
         d2[pos] = dd;
         id[pos] = o;
+    }
+    __device__ __forceinline__ void push(double dd, int32_t o, int k) {
+        if (cnt == k) {
+            if (gt(dd, o, d2[0], id[0]) || (dd == d2[0] && o == id[0])) return;
+            sift_down(dd, o, k);
+            return;
+        }
+        int pos = cnt++;
+        while (pos > 0) {
+            const int par = (pos - 1) >> 1;
+            if (!gt(dd, o, d2[par], id[par])) break;
+            d2[pos] = d2[par];
+            id[pos] = id[par];
+            pos = par;
+        }
+        d2[pos] = dd;
+        id[pos] = o;
+    }
+    // the current k-th smallest squared distance (valid once cnt == k)
+    __device__ __forceinline__ double worst() const { return d2[0]; }
+    __device__ __forceinline__ void finish() {
+        for (int end = cnt - 1; end > 0; --end) {
+            const double dd = d2[end];
+            const int32_t o = id[end];
+            d2[end] = d2[0];
+            id[end] = id[0];
+            sift_down(dd, o, end);
+        }
     }
 };
 
@@ -192,9 +226,10 @@ __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
             }
             if (whole) break;
             R -= 1e-9 * cs;
-            if (tk.cnt >= a.k && R > 0.0 && tk.d2[a.k - 1] < R * R) break;
+            if (tk.cnt >= a.k && R > 0.0 && tk.worst() < R * R) break;
         }
     }
+    tk.finish();
     const int64_t row = a.crow[t];
     for (int s = 0; s < a.k; ++s) a.out[row * a.k + s] = s < tk.cnt ? tk.id[s] : -1;
 }
