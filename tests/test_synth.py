@@ -103,3 +103,49 @@ def test_line_seeded_periodic_nodes():
     assert 0.9 < xyz.shape[0] / (L * L) < 1.1
     xyz2, _, _, _ = _n.line_seeded_periodic(L, h, seed=7)
     assert np.array_equal(xyz, xyz2)
+
+
+def test_curved_wall_node_sets():
+    import math
+    from synth import nodes
+    # annulus: wall nodes exactly on both circles, the rest strictly between
+    x, f, hm = nodes.disk_nodes(1.0, 0.05, R_in=0.5)
+    r = np.hypot(x[:, 0], x[:, 1])
+    wall = f != 0
+    assert np.allclose(np.sort(r[wall])[[0, -1]], [0.5, 1.0])
+    assert (np.isclose(r[wall], 0.5) | np.isclose(r[wall], 1.0)).all()
+    assert ((r[~wall] > 0.5) & (r[~wall] < 1.0)).all()
+    # the disk generator without an inner circle is unchanged by the option
+    a, fa, _ = nodes.disk_nodes(1.0, 0.05)
+    b, fb, _ = nodes.disk_nodes(1.0, 0.05, R_in=0.0)
+    assert np.array_equal(a, b) and np.array_equal(fa, fb)
+    # ball: Fibonacci wall nodes on the sphere, interior at least h/2 inside
+    x3, f3, h3 = nodes.ball_nodes(1.0, 0.2)
+    r3 = np.sqrt((x3 ** 2).sum(1))
+    assert np.allclose(r3[f3 != 0], 1.0)
+    assert (r3[f3 == 0] < 1.0 - 0.1 + 1e-12).all()
+    assert (f3 != 0).sum() == round(4 * math.pi / 0.04)
+
+
+def test_cavity_modes_satisfy_their_wall_conditions():
+    from synth import fields
+    th = np.linspace(0, 2 * np.pi, 37)[:-1]
+    for R in (1.0, 0.5):
+        pts = np.stack([R * np.cos(th), R * np.sin(th)], 1)
+        # coaxial TM_01: Ez vanishes on both circles; TE_01: E is azimuthal and vanishes there
+        E, H, _ = fields.coax_mode(pts, 0.3, 0.25, pol="TM")
+        assert np.abs(E).max() < 1e-12
+        E, Hz, _ = fields.coax_mode(pts, 0.3, 0.25, pol="TE")
+        assert np.abs(E).max() < 1e-12
+    ring = np.stack([np.cos(th), np.sin(th)], 1)
+    E, Hz, _ = fields.te01_disk(ring, 0.3, 0.25)
+    assert np.abs(E).max() < 1e-12
+    # PEC sphere mode: E = 0 on the sphere, and E is tangential everywhere
+    rs = np.random.default_rng(0)
+    u = rs.standard_normal((50, 3))
+    u /= np.sqrt((u ** 2).sum(1))[:, None]
+    E, H, _ = fields.sphere_mode(u, 0.2, 0.15)
+    assert np.abs(E).max() < 1e-12
+    inner = 0.6 * u
+    E, H, _ = fields.sphere_mode(inner, 0.2, 0.15)
+    assert np.abs((E * inner).sum(1)).max() < 1e-12 and np.abs(E).max() > 1e-3
