@@ -605,7 +605,10 @@ __global__ __launch_bounds__(256, 3) void k_wreg(WArgs a) {
     __shared__ double s_scale;
     const int64_t c = a.c0 + blockIdx.x;
     if (c >= a.Nt) return;                       // uniform over the workgroup
-    const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+    // thread (tr, tc): the 16 threads of one register column tc are 16
+    // consecutive lanes of one wavefront, so the column steps of the
+    // elimination run in a single wavefront
+    const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
     const int n = a.n, R = n + a.M, d = a.d;
     const int lda = R + a.nrhs;
 
@@ -671,48 +674,40 @@ __global__ __launch_bounds__(256, 3) void k_wreg(WArgs a) {
     bool bad = false;
     for (int k = 0; k < R; ++k) {
         const int bk = k >> 4, ck = k & 15;
-        double best = -1.0, bval = 0.0;
-        int bi = R;
-        if (tc == ck) {
-            double colk[WREG_B];
-            reg_col(m, bk, colk);
+        if ((tid >> 6) == (ck >> 2)) {           // the wavefront holding column k
+            double best = -1.0, bval = 0.0;
+            int bi = R;
+            if (tc == ck) {
+                double colk[WREG_B];
+                reg_col(m, bk, colk);
 #pragma unroll
-            for (int ra = 0; ra < WREG_B; ++ra) {
-                const int i = tr + WREG_T * ra;
-                const double v = colk[ra];
-                const bool take = (i < R) & (kof[i] < 0) & (fabs(v) > best);
-                best = take ? fabs(v) : best;
-                bval = take ? v : bval;
-                bi = take ? i : bi;
+                for (int ra = 0; ra < WREG_B; ++ra) {
+                    const int i = tr + WREG_T * ra;
+                    const double v = colk[ra];
+                    const bool take = (i < R) & (kof[i] < 0) & (fabs(v) > best);
+                    best = take ? fabs(v) : best;
+                    bval = take ? v : bval;
+                    bi = take ? i : bi;
+                }
+            }
+            // reduce over the 16 lanes of each column (lanes 16 q .. 16 q + 15)
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                const double ob = __shfl_xor(best, off, 64), ov = __shfl_xor(bval, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                const bool take = (ob > best) | ((ob == best) & (oi < bi));
+                best = take ? ob : best;
+                bval = take ? ov : bval;
+                bi = take ? oi : bi;
+            }
+            if (tid == (ck << 4)) {               // tr = 0 of column ck
+                cval[0] = bval;
+                cidx[0] = bi;
             }
         }
-        // the four thread rows of a wavefront hold lanes tc, tc + 16, tc + 32,
-        // tc + 48: reduce over them, one candidate per wavefront into LDS
-#pragma unroll
-        for (int off = 16; off <= 32; off <<= 1) {
-            const double ob = __shfl_xor(best, off, 64), ov = __shfl_xor(bval, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            const bool take = (ob > best) | ((ob == best) & (oi < bi));
-            best = take ? ob : best;
-            bval = take ? ov : bval;
-            bi = take ? oi : bi;
-        }
-        if ((tid & 63) == ck) {
-            cval[tid >> 6] = bval;
-            cidx[tid >> 6] = bi;
-        }
         __syncthreads();
-        double pbest = -1.0, pval = 0.0;
-        int p = R;
-#pragma unroll
-        for (int t = 0; t < 256 / 64; ++t) {
-            const int ii = cidx[t];
-            const double vv = cval[t], av = fabs(vv);
-            const bool take = (ii < R) & ((av > pbest) | ((av == pbest) & (ii < p)));
-            pbest = take ? av : pbest;
-            pval = take ? vv : pval;
-            p = take ? ii : p;
-        }
+        const int p = cidx[0];
+        const double pval = cval[0], pbest = p < R ? fabs(pval) : -1.0;
         if (!(pbest > 0.0)) {                    // the same decision in every thread
             bad = true;
             break;
