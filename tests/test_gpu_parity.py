@@ -682,3 +682,37 @@ def test_graph_replays_with_eager_work_between_them():
             assert (s.E_original(sg) == s.E_original(se)).all(), (prec, rep)
             assert (s.H_original(sg) == s.H_original(se)).all(), (prec, rep)
             assert (og["energy"] == oe["energy"]).all(), (prec, rep)
+
+
+@pytest.mark.parametrize("n,m", [(12, 2), (100, 4)])
+def test_duplicate_node_is_reported_as_singular(n, m):
+    # two nodes at the same position make identical rows in every local
+    # system that holds both: the set-up reports RBFFD_ESINGULAR (the
+    # register solver for n = 12, the LDS solver for n = 100) instead of
+    # returning weights; the kernels exit normally
+    from paper_2508_18205_amd._abi import RbffdError
+    _announce(f"duplicate node -> singular (n={n})")
+    xyz, flags, h = nodes.jittered_grid((21, 21), seed=3)
+    xyz = np.concatenate([xyz, xyz[200:201]])
+    flags = np.concatenate([flags, flags[200:201]])
+    w = configs.Workload("duplicate", 2, xyz, flags, h, n, m, 2, 31, 1e-3, 10)
+    with pytest.raises(RbffdError) as ei:
+        Solver.from_workload(w, precision="f64")
+    _announce(f"  {ei.value}")
+    assert ei.value.code == _abi.ESINGULAR
+
+
+def test_collinear_nodes_give_a_zero_pivot():
+    # every node on the line y = 0.5: the monomials y, xy, y^2 vanish on each
+    # stencil, the local systems are singular, and the elimination's zero
+    # pivot is reported as RBFFD_ESINGULAR naming a node
+    from paper_2508_18205_amd._abi import RbffdError
+    _announce("collinear nodes -> zero pivot")
+    x = (np.arange(60) + 0.5) / 60.0
+    xyz = np.stack([x, np.full_like(x, 0.5)], 1)
+    flags = np.zeros(60, np.uint8)
+    w = configs.Workload("collinear", 2, xyz, flags, 1 / 60, 12, 2, 2, 31, 1e-3, 10, bc="PERIODIC")
+    with pytest.raises(RbffdError) as ei:
+        Solver.from_workload(w, precision="f64")
+    _announce(f"  {ei.value}")
+    assert ei.value.code == _abi.ESINGULAR and "singular local system at internal node" in str(ei.value)
