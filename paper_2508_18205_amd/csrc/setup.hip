@@ -559,9 +559,10 @@ __global__ __launch_bounds__(1024) void k_weights(WArgs a) {
 // registers.  Gauss-Jordan elimination with partial pivoting (largest |value|
 // among the rows not yet used as pivots, ties to the lower row): one barrier
 // after the pivot candidates, one after the pivot row and the multipliers are
-// published in LDS, per column; no back substitution.  The LDS footprint is a
-// few KB, so several systems share a CU (the LDS-resident kernel holds one
-// 106-unknown system per CU).
+// published in LDS, per column; no back substitution.  The LDS footprint is
+// ~20 KB (mostly the assembly band), so registers, not LDS, set how many
+// systems share a CU (the LDS-resident kernel holds one 106-unknown system
+// per CU).
 constexpr int WREG_T = 16, WREG_BMAX = 7, WREG_MAX = WREG_T * WREG_BMAX;
 
 // Column b / row r of the register block for an index that is the same in
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(256, 3) void k_wreg(WArgs a) {
     __shared__ double xi[WREG_MAX * 3];
     __shared__ double band[WREG_T * WREG_MAX];   // one 16-row band during assembly
     __shared__ double prow[WREG_MAX], mcol[WREG_MAX], dpiv[WREG_MAX];
-    __shared__ double cval[WREG_T];
+    __shared__ double cval[WREG_T];              // [0]: the pivot candidate of column k
     __shared__ int cidx[WREG_T];
     __shared__ int kof[WREG_MAX];                // column pivoted on row i, -1 before
     __shared__ double s_scale;
