@@ -161,3 +161,18 @@ def test_wall_normals_validation_on_host():
     n3[w3[0]] = (0.0, 0.6, 0.7)
     assert lib.rbffd_set_wall_normals(plan, n3.ctypes.data) == _abi.EINVAL
     lib.rbffd_plan_destroy(plan)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # the product path has no CPU fallback: without librbffd.so the binding
+    # raises instead of computing anything
+    from paper_2508_18205_amd import _abi
+    monkeypatch.setattr(_abi, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "librbffd.so"))
+    monkeypatch.setattr(_abi, "_lib", None)
+    with pytest.raises(ImportError):
+        _abi.load()
+    from paper_2508_18205_amd import Solver
+    from synth import configs
+    w = configs.tm_cavity_2d(scale=0.3)
+    with pytest.raises((ImportError, RuntimeError)):
+        Solver.from_workload(w)
