@@ -336,6 +336,18 @@ int rbffd_energy(const rbffd_plan* plan, const void* E, const void* Ha, const vo
                  double* out, void* workspace, void* stream);
 int rbffd_compare(const rbffd_plan* plan, int32_t which, const void* field, const double* ref,
                   double* out, void* workspace, void* stream);
+/* rbffd_energy_static: rbffd_energy without a workspace argument and without
+ * any allocation, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments and result as rbffd_energy (the same kernels, so the same
+ * bits).  Its scratch -- the FP64 partial sums of at most 1024 reduction
+ * blocks, 8 KB -- is a device array inside the library, one per GPU, held
+ * until the process ends; the node count is not limited by it.  Calls that
+ * overlap on one GPU share that array and race: serialise them (one stream,
+ * or events).  Errors as rbffd_energy; RBFFD_EHIP if the array's address
+ * cannot be obtained on the stream's device. */
+int rbffd_energy_static(const rbffd_plan* plan, const void* E, const void* Ha, const void* Hb,
+                        double* out, void* stream);
 
 /* ---- launch tuning ---------------------------------------------------------
  * Times the step kernels' launch variants on the current device with the

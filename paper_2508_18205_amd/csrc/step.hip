@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -1661,6 +1662,65 @@ extern "C" int rbffd_energy(const rbffd_plan* p, const void* E, const void* Ha, 
     if (p->K > 1) return set_err(p, RBFFD_ENOTSUP, "energy of a K-field batch: use rbffd_compare per field");
     RunWS w = run_ws(ws);
     energy(p, E, Ha, Hb, out, w, nullptr, 1, (hipStream_t)stream);
+    HIPCHK(p, hipGetLastError());
+    return RBFFD_OK;
+}
+
+// ---- energy without a workspace ------------------------------------------------
+// rbffd_energy_static runs the same two kernels as rbffd_energy, with the
+// per-block FP64 partial sums in this file-scope device array instead of the
+// caller's workspace.  Every device holds its own copy at its own address;
+// host code uses only that address (looked up once per device), never the
+// array's name.  The reduction writes partial b for every block b < nb before
+// the second kernel reads partials 0 .. nb - 1, so nothing must start at zero;
+// calls that overlap on one device share the array and race.
+namespace {
+constexpr int kStaticParts = RED_BLOCKS;   // 8 KB of partial sums per device
+static __device__ __align__(256) double energy_scratch[kStaticParts];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for(const rbffd_plan* p, hipStream_t st, double** out) {
+    int dev = -1;
+    if (st) {
+        HIPCHK(p, hipStreamGetDevice(st, &dev));
+    } else {
+        HIPCHK(p, hipGetDevice(&dev));
+    }
+    if (dev < 0 || dev >= kMaxDevices) return set_err(p, RBFFD_ESIZE, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        HIPCHK(p, hipGetDevice(&cur));
+        if (cur != dev) HIPCHK(p, hipSetDevice(dev));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(energy_scratch));
+        if (cur != dev) HIPCHK(p, hipSetDevice(cur));
+        if (e != hipSuccess || !ptr)
+            return set_err(p, RBFFD_EHIP, std::string("hipGetSymbolAddress(energy_scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return RBFFD_OK;
+}
+}  // namespace
+
+extern "C" int rbffd_energy_static(const rbffd_plan* p, const void* E, const void* Ha, const void* Hb, double* out,
+                                   void* stream) {
+    if (!p || !E || !Ha || !Hb || !out) return RBFFD_EINVAL;
+    if (!p->ready) return set_err(p, RBFFD_ESTATE, "rbffd_weights has not run");
+    if (p->K > 1) return set_err(p, RBFFD_ENOTSUP, "energy of a K-field batch: use rbffd_compare per field");
+    const int64_t nmax = std::max(p->E.N, p->H.N);
+    if (std::min<int64_t>(RED_BLOCKS, cdiv(nmax, 256)) > kStaticParts)
+        return set_err(p, RBFFD_ESIZE, "more reduction blocks than the static scratch holds");
+    hipStream_t st = (hipStream_t)stream;
+    double* parts = nullptr;
+    int rc = scratch_for(p, st, &parts);
+    if (rc) return rc;
+    RunWS w{};
+    w.part = parts;
+    energy(p, E, Ha, Hb, out, w, nullptr, 1, st);
     HIPCHK(p, hipGetLastError());
     return RBFFD_OK;
 }
