@@ -422,6 +422,15 @@ __device__ __forceinline__ double system_entry(const WArgs& a, const double* xi,
     return v;
 }
 
+// A pivot no larger than 1024 R eps max_ij |A~_ij| (R unknowns, eps the FP64
+// machine epsilon, A~ the scaled system before elimination) marks the local
+// system as numerically singular: every valid stencil of the benchmarked node
+// sets keeps its pivots above ~1e8 R eps max|A~| (condition numbers up to
+// ~1e7), while collinear stencils and nodes closer than ~1e-11 h fall below.
+__device__ __forceinline__ double pivot_floor(int R, double amax) {
+    return 1024.0 * (double)R * 2.220446049250313e-16 * amax;
+}
+
 __global__ __launch_bounds__(1024) void k_weights(WArgs a) {
     extern __shared__ double lds[];
     const int64_t c = a.c0 + blockIdx.x;
@@ -479,6 +488,16 @@ __global__ __launch_bounds__(1024) void k_weights(WArgs a) {
         Am[i * lda + j] = v;
     }
     __syncthreads();
+    // singularity threshold relative to the scaled system's largest entry
+    __shared__ double s_tau;
+    if (tid < 64) {
+        double mx = 0.0;
+        for (int e = tid; e < R * R; e += 64) mx = fmax(mx, fabs(Am[(e / R) * lda + e % R]));
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+        if (tid == 0) s_tau = pivot_floor(R, mx);
+    }
+    __syncthreads();
+    const double tau = s_tau;
 
     // 3. forward elimination with partial pivoting.  Rows are addressed
     // through prm (logical row -> row of Am), so a pivot exchange is a swap of
@@ -503,7 +522,7 @@ __global__ __launch_bounds__(1024) void k_weights(WArgs a) {
             }
             // every lane now holds the pivot's logical row bi
             const int rk = prm[k], rp = prm[bi];
-            if (!(best > 0.0)) {
+            if (!(best > tau)) {
                 if (tid == 0) s_bad = 1;
             } else {
                 const double pk = Am[rp * lda + k];
@@ -668,6 +687,24 @@ __global__ __launch_bounds__(256, 3) void k_wreg(WArgs a) {
         __syncthreads();
     }
 
+    // singularity threshold relative to the largest entry of the square
+    // system: a wavefront maximum, then the four wavefronts' through LDS
+    double tau;
+    {
+        double mx = 0.0;
+#pragma unroll
+        for (int ra = 0; ra < WREG_B; ++ra)
+#pragma unroll
+            for (int cb = 0; cb < WREG_B; ++cb) {
+                const bool in = (tr + WREG_T * ra < R) & (tc + WREG_T * cb < R);
+                mx = in ? fmax(mx, fabs(m[ra][cb])) : mx;
+            }
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+        if ((tid & 63) == 0) cval[tid >> 6] = mx;
+        __syncthreads();
+        tau = pivot_floor(R, fmax(fmax(cval[0], cval[1]), fmax(cval[2], cval[3])));
+        __syncthreads();                         // cval is reused by the pivot search
+    }
     // 3. Gauss-Jordan elimination.  The padding rows (i >= R) and columns
     // (j >= lda) hold zeros and stay zero, so every step below is written
     // without per-element branches: predicates become selects and LDS reads
@@ -709,7 +746,7 @@ __global__ __launch_bounds__(256, 3) void k_wreg(WArgs a) {
         __syncthreads();
         const int p = cidx[0];
         const double pval = cval[0], pbest = p < R ? fabs(pval) : -1.0;
-        if (!(pbest > 0.0)) {                    // the same decision in every thread
+        if (!(pbest > tau)) {                    // the same decision in every thread
             bad = true;
             break;
         }

@@ -716,3 +716,57 @@ def test_collinear_nodes_give_a_zero_pivot():
         Solver.from_workload(w, precision="f64")
     _announce(f"  {ei.value}")
     assert ei.value.code == _abi.ESINGULAR and "singular local system at internal node" in str(ei.value)
+
+
+@pytest.mark.parametrize("n,m,alpha", [(12, 2, 2), (100, 4, 0)])
+def test_tilted_collinear_nodes_are_singular(n, m, alpha):
+    # every node on the tilted line y = 0.3 x + 0.1: on each stencil the
+    # monomial y equals 0.3 x + 0.1, so every local system is singular, but
+    # rounding leaves pivots of ~1e-16 of the system's scale instead of exact
+    # zeros; the relative pivot floor reports them (the register solver for
+    # n = 12, the LDS solver for n = 100 with no HV system); kernels exit
+    # normally
+    from paper_2508_18205_amd._abi import RbffdError
+    _announce(f"tilted collinear nodes -> singular (n={n})")
+    x = (np.arange(150) + 0.5) / 150.0
+    xyz = np.stack([x, 0.3 * x + 0.1], 1)
+    w = configs.Workload("tilted", 2, xyz, np.zeros(150, np.uint8), 1 / 150, n, m, alpha,
+                         31 if alpha else 0, 1e-3, 10)
+    with pytest.raises(RbffdError) as ei:
+        Solver.from_workload(w, precision="f64")
+    _announce(f"  {ei.value}")
+    assert ei.value.code == _abi.ESINGULAR and "singular local system at internal node" in str(ei.value)
+
+
+@pytest.mark.parametrize("n,m,alpha", [(12, 2, 2), (100, 4, 0)])
+def test_near_duplicate_nodes_are_singular(n, m, alpha):
+    # a node 1e-13 h from another: not a duplicate position, but the two rows
+    # of every local system holding both agree to ~1e-13, far below what the
+    # FP64 weights can resolve; reported as RBFFD_ESINGULAR by both solvers
+    from paper_2508_18205_amd._abi import RbffdError
+    _announce(f"near-duplicate node -> singular (n={n})")
+    xyz, flags, h = nodes.jittered_grid((21, 21), seed=3)
+    xyz = np.concatenate([xyz, xyz[200:201] + 1e-13 * h * np.array([[0.6, 0.8]])])
+    flags = np.concatenate([flags, flags[200:201]])
+    w = configs.Workload("near_duplicate", 2, xyz, flags, h, n, m, alpha, 31 if alpha else 0, 1e-3, 10)
+    with pytest.raises(RbffdError) as ei:
+        Solver.from_workload(w, precision="f64")
+    _announce(f"  {ei.value}")
+    assert ei.value.code == _abi.ESINGULAR and "singular local system at internal node" in str(ei.value)
+
+
+def test_well_conditioned_neighbours_of_the_floor_still_solve():
+    # the same grid with the extra node 1e-6 h away (pivots far above the
+    # floor): the set-up succeeds and the weights reproduce d/dx of x
+    _announce("node 1e-6 h from another -> solvable")
+    xyz, flags, h = nodes.jittered_grid((21, 21), seed=3)
+    xyz = np.concatenate([xyz, xyz[200:201] + 1e-6 * h * np.array([[0.6, 0.8]])])
+    flags = np.concatenate([flags, flags[200:201]])
+    w = configs.Workload("near_node", 2, xyz, flags, h, 12, 2, 0, 0, 1e-3, 10)
+    s = Solver.from_workload(w, precision="f64")
+    wc = s.weights(_abi.OP_CURL_H)
+    st = s.stencils()[:, :12]
+    X = xyz[s.perm]
+    dx = (wc[:, 0, :] * (X[st, 0] - X[:, None, 0])).sum(1)
+    dy = (wc[:, 1, :] * (X[st, 1] - X[:, None, 1])).sum(1)
+    assert np.abs(dx - 1.0).max() < 1e-6 and np.abs(dy - 1.0).max() < 1e-6
