@@ -87,3 +87,13 @@ int oracle_threads(void) {
     }
     return t;
 }
+
+/* Sets the OpenMP thread count of later calls (the benchmark's one-core
+ * figure); values below 1 are ignored. */
+void oracle_set_threads(int t) {
+#ifdef _OPENMP
+    if (t >= 1) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}

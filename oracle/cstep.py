@@ -47,6 +47,8 @@ def load():
                                        P]
     lib.oracle_threads.restype = C.c_int
     lib.oracle_threads.argtypes = []
+    lib.oracle_set_threads.restype = None
+    lib.oracle_set_threads.argtypes = [C.c_int]
     _lib = lib
     return lib
 
@@ -54,6 +56,11 @@ def load():
 def threads():
     """OpenMP threads the C oracle runs on."""
     return int(load().oracle_threads())
+
+
+def set_threads(t):
+    """OpenMP threads of later calls."""
+    load().oracle_set_threads(int(t))
 
 
 class Operator:

@@ -70,3 +70,46 @@ def run_workload(w, op_h, op_e, steps=None, energy_every=0, use_eps=True, src=Tr
     nrm = w.normals if (w.bc == "PEC" and w.dim == 3) else None
     return _step.run(w.E0, w.H0, op_h, op_e, w.dt, steps, gamma, kappa, keep, mu0=w.mu0,
                      eps0=w.eps0, h_e=w.h, h_h=h_h, energy_every=energy_every, src=s, rcv=r, normals=nrm)
+
+
+# ---------------------------------------------------------------------------
+# Large node sets: the same weights, computed for slices of the centres in
+# worker processes (fork start method; the inputs are inherited, each worker
+# fills its rows of shared output arrays).  No arithmetic differs from the
+# single-process calls: every row is one local system of weights.py.
+# ---------------------------------------------------------------------------
+_PW = {}
+
+
+def _pw_rows(args):
+    import numpy as _np
+    b0, b1 = args
+    g = _PW
+    xyz, st = g["xyz"], g["st"]
+    cw = _np.frombuffer(g["cw"], dtype=_np.float64).reshape(-1, xyz.shape[1], g["n"])
+    cw[b0:b1] = _w.curl_weights(xyz, xyz[b0:b1], st[b0:b1, :g["n"]], g["m"])
+    if g["alpha"] > 0:
+        hw = _np.frombuffer(g["hw"], dtype=_np.float64).reshape(-1, g["n_hv"])
+        hw[b0:b1] = _w.hv_weights(xyz, xyz[b0:b1], st[b0:b1, :g["n_hv"]], g["alpha"])
+    return b1 - b0
+
+
+def weights_parallel(xyz, stencils, n, m, n_hv, alpha, procs, chunk=16384):
+    """(curl_w [N, d, n], hv_w [N, n_hv]) of the collocated RBF-FD operators
+    for every node, from the stencil rows ``stencils`` (nearest first), with
+    ``procs`` worker processes."""
+    import multiprocessing as mp
+    N, d = xyz.shape
+    cw_buf = mp.RawArray("d", N * d * n)
+    hw_buf = mp.RawArray("d", max(1, N * n_hv if alpha > 0 else 1))
+    _PW.clear()
+    _PW.update(xyz=xyz, st=stencils, cw=cw_buf, hw=hw_buf, n=n, m=m, n_hv=n_hv, alpha=alpha)
+    jobs = [(b, min(N, b + chunk)) for b in range(0, N, chunk)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(max(1, int(procs))) as pool:
+        done = sum(pool.map(_pw_rows, jobs))
+    assert done == N
+    cw = np.frombuffer(cw_buf, dtype=np.float64).reshape(N, d, n)
+    hw = np.frombuffer(hw_buf, dtype=np.float64).reshape(N, n_hv) if alpha > 0 else None
+    _PW.clear()
+    return cw, hw
