@@ -65,6 +65,11 @@ extern "C" {
 #define RBFFD_F64  0
 #define RBFFD_F32  1
 #define RBFFD_BF16 2          /* field storage only; arithmetic in FP32       */
+#define RBFFD_W22  3          /* weight storage only (wdtype): compressed FP32
+                                 weights, four 22-bit mantissas and one shared
+                                 exponent per 4-slot chunk (12 bytes instead of
+                                 16); FP32 fields and arithmetic; 2D collocated
+                                 single-field plans without the adjoint      */
 
 /* Which operator rbffd_get_weights / rbffd_set_weights address.  For the
  * two-set variant the *_H operators are the ones applied in the H update
@@ -93,7 +98,7 @@ typedef struct rbffd_params {
     int32_t n_hv;       /* HV stencil size; 0 = 2 * C(2 alpha + dim, dim) + 1      */
     int32_t bc;         /* RBFFD_BC_*                                             */
     int32_t reorder;    /* RBFFD_ORDER_*                                          */
-    int32_t wdtype;     /* stored weight precision for the step: F64 or F32        */
+    int32_t wdtype;     /* stored weight precision for the step: F64, F32 or W22   */
     int32_t fdtype;     /* field storage: F64, F32 or BF16 (BF16 needs F32 weights)*/
     int32_t K;          /* independent fields per batch (1 = single field; 2D)    */
     int32_t adjoint;    /* nonzero: also build transposed operators (2D, K = 1)   */

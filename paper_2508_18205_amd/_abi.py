@@ -10,6 +10,7 @@ MODE = {"FD": 0, "VFD": 1, "STAG2": 2}
 BC = {"PEC": 0, "PERIODIC": 1}
 ORDER = {"NONE": 0, "MORTON": 1, "RCM": 2}
 DTYPE = {"f64": 0, "f32": 1, "bf16": 2}
+W22 = 3            # weight storage (wdtype): compressed FP32 weights
 OP_CURL_H, OP_HV_H, OP_CURL_E, OP_HV_E = 0, 1, 2, 3
 ST_UNION, ST_CURL_H, ST_HV_H, ST_CURL_E, ST_HV_E = 0, 1, 2, 3, 4
 

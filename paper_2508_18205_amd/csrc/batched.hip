@@ -601,20 +601,10 @@ int batched_run(const rbffd_plan* p, rbffd_fields* f, const rbffd_run_args* a, v
     RunWS w = run_ws(ws);
     if (eo) hipLaunchKernelGGL(k_bctr_set, dim3(1), dim3(64), 0, st, w.ctr, 0);
     int s = 0;
-    if (a->use_graph && a->T >= 4) {
-        hipGraph_t g;
-        hipGraphExec_t ge;
-        hipStream_t cs;
-        int rc = capture_stream(p, &cs);
+    if (a->use_graph) {
+        const int rc = replay_steps(
+            p, a->T, f->cur, st, [&](int c, hipStream_t cs) { full_step_b(p, f, c, eo, every, &w, cs); }, &s);
         if (rc) return rc;
-        HIPCHK(p, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        full_step_b(p, f, f->cur, eo, every, &w, cs);
-        full_step_b(p, f, 1 - f->cur, eo, every, &w, cs);
-        HIPCHK(p, hipStreamEndCapture(cs, &g));
-        HIPCHK(p, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-        for (; s + 2 <= a->T; s += 2) HIPCHK(p, hipGraphLaunch(ge, st));
-        HIPCHK(p, hipGraphExecDestroy(ge));
-        HIPCHK(p, hipGraphDestroy(g));
     }
     for (; s < a->T; ++s) {
         full_step_b(p, f, f->cur, eo, every, &w, st);

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -182,6 +184,40 @@ int refill_transpose(rbffd_plan* p, hipStream_t s);
 int build_halos(rbffd_plan* p, void* ws, hipStream_t s);
 int64_t setup_ws_bytes(const rbffd_plan* p);
 int capture_stream(const rbffd_plan* p, hipStream_t* out);
+
+// ---- HIP-graph step loop -----------------------------------------------------
+// The step loop of rbffd_run is replayed from HIP graphs: one graph of S
+// captured steps (S even, at most RBFFD_GRAPH_STEPS) replayed T / S times,
+// then one graph of the remaining whole step pairs.  rec(c, stream) records
+// one full step reading buffer set c; the buffers alternate within a graph
+// and, S being even, every replay leaves them as it found them.  *done
+// receives the number of steps replayed (even); the caller runs the rest.
+#define RBFFD_GRAPH_STEPS 64
+template <typename Rec>
+int replay_steps(const rbffd_plan* p, int T, int cur, hipStream_t st, Rec rec, int* done) {
+    *done = 0;
+    if (T < 4) return RBFFD_OK;
+    hipStream_t cs;
+    int rc = capture_stream(p, &cs);
+    if (rc) return rc;
+    int left = T;
+    while (left >= 4) {
+        const int S = std::min(left & ~1, RBFFD_GRAPH_STEPS);
+        hipGraph_t g;
+        hipGraphExec_t ge;
+        HIPCHK(p, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < S; ++k) rec((cur + k) & 1, cs);
+        HIPCHK(p, hipStreamEndCapture(cs, &g));
+        HIPCHK(p, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        const int reps = left / S;
+        for (int r = 0; r < reps; ++r) HIPCHK(p, hipGraphLaunch(ge, st));
+        HIPCHK(p, hipGraphExecDestroy(ge));
+        HIPCHK(p, hipGraphDestroy(g));
+        left -= reps * S;
+        *done += reps * S;
+    }
+    return RBFFD_OK;
+}
 
 // XCD-aware mapping of a linear workgroup id: consecutive logical ids land on
 // the same XCD (round-robin dispatch sends block b to XCD b % 8), so

@@ -4,6 +4,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "wpack.h"
 
 int set_err(const rbffd_plan* p, int code, const std::string& msg) {
     if (p) const_cast<rbffd_plan*>(p)->err = msg;
@@ -82,7 +83,7 @@ void layout_set(Bump& b, NodeSet& S, int dim, bool is_e, bool normals) {
     S.nrm = normals ? b.take<double>(S.N * dim) : nullptr;
 }
 
-void layout_block(Bump& b, OpBlock& o, int dim, int wb, int K, bool adjoint) {
+void layout_block(Bump& b, OpBlock& o, int dim, int wb, int cb, int K, bool adjoint) {
     o.tiles = cdiv(o.Nt, RBFFD_TILE);
     o.C4 = (int)cdiv(o.n - 1, 4);
     o.V4 = o.nh > 0 ? (int)cdiv(o.nh - 1, 4) : 0;
@@ -106,8 +107,8 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int K, bool adjoint) {
     }
     o.wc = b.take<double>(o.Nt * dim * o.n);
     o.wh = o.nh > 0 ? b.take<double>(o.Nt * o.nh) : nullptr;
-    o.pwc = b.take_bytes(T * o.C4 * dim * 4 * wb);
-    o.pwh = b.take_bytes(T * std::max(o.V4, 0) * 4 * wb);
+    o.pwc = b.take_bytes(T * o.C4 * dim * cb);
+    o.pwh = b.take_bytes(T * std::max(o.V4, 0) * cb);
     if (K > 1) {
         o.bidx = b.take<int32_t>(o.Nt * o.S4 * 4);
         o.bwc = b.take<float>(o.Nt * dim * o.C4 * 4);
@@ -131,8 +132,9 @@ int64_t layout_arena(rbffd_plan* p, char* base, int64_t* ws, int64_t* adj_ws) {
     const int wb = weight_elem_bytes(p->p.wdtype);
     layout_set(b, p->E, p->dim, true, has_wall_normals(p));
     if (!p->collocated) layout_set(b, p->H, p->dim, false, false);
-    layout_block(b, p->opH, p->dim, wb, p->K, p->p.adjoint != 0);
-    if (!p->collocated) layout_block(b, p->opE, p->dim, wb, p->K, false);
+    const int cb = chunk_bytes(p->p.wdtype);
+    layout_block(b, p->opH, p->dim, wb, cb, p->K, p->p.adjoint != 0);
+    if (!p->collocated) layout_block(b, p->opE, p->dim, wb, cb, p->K, false);
     else {
         // the E update uses the same operator block
         OpBlock keep = p->opE;
@@ -176,9 +178,15 @@ extern "C" int rbffd_plan_create(const rbffd_params* prm, int64_t N, const doubl
     if (q.hv_alpha < 0 || q.hv_alpha > 3) return fail(RBFFD_ENOTSUP, "hv_alpha must be 0..3");
     if (q.h <= 0) return fail(RBFFD_EINVAL, "h must be positive");
     if (q.eps0 <= 0 || q.mu0 <= 0) return fail(RBFFD_EINVAL, "eps0 and mu0 must be positive");
-    if (q.wdtype != RBFFD_F64 && q.wdtype != RBFFD_F32) return fail(RBFFD_EINVAL, "wdtype must be F64 or F32");
+    if (q.wdtype != RBFFD_F64 && q.wdtype != RBFFD_F32 && q.wdtype != RBFFD_W22)
+        return fail(RBFFD_EINVAL, "wdtype must be F64, F32 or W22");
+    if (q.wdtype == RBFFD_W22 &&
+        (q.fdtype != RBFFD_F32 || q.dim != 2 || q.mode == RBFFD_MODE_STAG2 || q.K != 1 || q.adjoint))
+        return fail(RBFFD_ENOTSUP, "W22 weights are implemented for 2D collocated single-field FP32 plans "
+                                   "without the adjoint");
     if (q.fdtype < 0 || q.fdtype > 2) return fail(RBFFD_EINVAL, "bad fdtype");
     if (q.fdtype == RBFFD_BF16 && q.wdtype != RBFFD_F32) return fail(RBFFD_EINVAL, "BF16 fields need F32 weights");
+    if (q.fdtype == RBFFD_F32 && q.wdtype == RBFFD_F64) return fail(RBFFD_EINVAL, "F32 fields need F32 or W22 weights");
     if (q.fdtype == RBFFD_F64 && q.wdtype != RBFFD_F64) return fail(RBFFD_EINVAL, "F64 fields need F64 weights");
     if (q.bc != RBFFD_BC_PEC && q.bc != RBFFD_BC_PERIODIC) return fail(RBFFD_EINVAL, "bad bc");
     if (q.reorder < 0 || q.reorder > 2) return fail(RBFFD_EINVAL, "bad reorder");

@@ -11,9 +11,11 @@
 #include <cstring>
 #include <numeric>
 #include <vector>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "common.h"
+#include "wpack.h"
 
 namespace {
 
@@ -828,18 +830,22 @@ __global__ void k_pack_union(const int32_t* st, const double* wc, const double* 
         pidx[(tile * S4 + q) * RBFFD_TILE + lane] = make_int4(v[0], v[1], v[2], v[3]);
     }
     for (int q = 0; q < C4; ++q)
-        for (int ax = 0; ax < d; ++ax)
+        for (int ax = 0; ax < d; ++ax) {
+            double w[4];
             for (int u = 0; u < 4; ++u) {
                 const int s = 1 + 4 * q + u;
-                const double w = (real && s < n) ? wc[(ic * d + ax) * n + s] : 0.0;
-                pwc[(((tile * C4 + q) * d + ax) * RBFFD_TILE + lane) * 4 + u] = (TW)w;
+                w[u] = (real && s < n) ? wc[(ic * d + ax) * n + s] : 0.0;
             }
-    for (int q = 0; q < V4; ++q)
+            WF<TW>::store(pwc + ((tile * C4 + q) * d + ax) * WF<TW>::CH + lane * WF<TW>::LS, w);
+        }
+    for (int q = 0; q < V4; ++q) {
+        double w[4];
         for (int u = 0; u < 4; ++u) {
             const int s = 1 + 4 * q + u;
-            const double w = (real && s < nh) ? wh[ic * nh + s] : 0.0;
-            pwh[((tile * V4 + q) * RBFFD_TILE + lane) * 4 + u] = (TW)w;
+            w[u] = (real && s < nh) ? wh[ic * nh + s] : 0.0;
         }
+        WF<TW>::store(pwh + (tile * V4 + q) * WF<TW>::CH + lane * WF<TW>::LS, w);
+    }
 }
 
 template <typename TW>
@@ -1059,23 +1065,23 @@ int cell_level(int64_t N, int d, int width) {
 // only matters for sizes reported before any GPU work.
 size_t sort_temp_bytes(int64_t N) {
     size_t t = 0;
-    if (hipcub::DeviceRadixSort::SortPairs(nullptr, t, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
-                                           (int32_t*)nullptr, (int)N, 0, 64) != hipSuccess)
+    if (rocprim::radix_sort_pairs(nullptr, t, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
+                                  (int32_t*)nullptr, (int)N, 0, 64) != hipSuccess)
         t = (size_t)N * 24 + (1u << 22);
     return t;
 }
 
 size_t scan_temp_bytes(int64_t E) {
     size_t t = 0;
-    if (hipcub::DeviceScan::ExclusiveSum(nullptr, t, (int32_t*)nullptr, (int32_t*)nullptr, (int)E) != hipSuccess)
+    if (rocprim::exclusive_scan(nullptr, t, (int32_t*)nullptr, (int32_t*)nullptr, (int32_t)0, (size_t)E,
+                                rocprim::plus<int32_t>()) != hipSuccess)
         t = (size_t)E / 64 + (1u << 22);
     return t;
 }
 
 size_t key_sort_temp_bytes(int64_t E) {
     size_t t = 0;
-    if (hipcub::DeviceRadixSort::SortKeys(nullptr, t, (uint64_t*)nullptr, (uint64_t*)nullptr, (int)E, 0, 64) !=
-        hipSuccess)
+    if (rocprim::radix_sort_keys(nullptr, t, (uint64_t*)nullptr, (uint64_t*)nullptr, (int)E, 0, 64) != hipSuccess)
         t = (size_t)E * 16 + (1u << 22);
     return t;
 }
@@ -1123,8 +1129,8 @@ int build_search(rbffd_plan* p, NodeSet& S, Search& s, hipStream_t st) {
     ma.vals = s.vals_in;
     hipLaunchKernelGGL(k_morton, dim3(blocks(S.N)), dim3(256), 0, st, ma);
     size_t tb = s.temp_bytes;
-    HIPCHK(p, hipcub::DeviceRadixSort::SortPairs(s.temp, tb, s.keys_in, s.keys, s.vals_in, s.sperm, (int)S.N, 0,
-                                                 d * bits, st));
+    HIPCHK(p, rocprim::radix_sort_pairs(s.temp, tb, s.keys_in, s.keys, s.vals_in, s.sperm, (int)S.N, 0,
+                                        (unsigned)(d * bits), st));
     hipLaunchKernelGGL(k_gather_sorted, dim3(blocks(S.N)), dim3(256), 0, st, S.xyz_in, s.sperm, S.N, d, s.sxyz);
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks(s.ncells)), dim3(256), 0, st, s.cstart, s.ncells, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks(s.ncells)), dim3(256), 0, st, s.cend, s.ncells, 0);
@@ -1483,7 +1489,11 @@ static int pack_block(rbffd_plan* p, const OpBlock& o, hipStream_t st) {
     const int64_t G = o.tiles * RBFFD_TILE;
     const bool f64 = p->p.wdtype == RBFFD_F64;
     if (!o.cross) {
-        if (f64)
+        if (p->p.wdtype == RBFFD_W22)
+            hipLaunchKernelGGL(k_pack_union<w22>, dim3(blocks(G)), dim3(256), 0, st, o.st_union, o.wc, o.wh, o.Nt,
+                               o.ns, o.n, o.nh, d, o.C4, o.V4, o.S4, o.tiles, (int4*)o.pidx, (w22*)o.pwc,
+                               (w22*)o.pwh);
+        else if (f64)
             hipLaunchKernelGGL(k_pack_union<double>, dim3(blocks(G)), dim3(256), 0, st, o.st_union, o.wc, o.wh, o.Nt,
                                o.ns, o.n, o.nh, d, o.C4, o.V4, o.S4, o.tiles, (int4*)o.pidx, (double*)o.pwc,
                                (double*)o.pwh);
@@ -1528,7 +1538,7 @@ int build_transpose(rbffd_plan* p, void* wsp, hipStream_t st) {
     hipLaunchKernelGGL(k_tkeys, dim3(blocks(E)), dim3(256), 0, st, o.st_union, N, (int)ns, kin);
     int end_bit = 1;
     while (end_bit < 64 && ((uint64_t)1 << end_bit) <= (uint64_t)(N * E)) ++end_bit;
-    HIPCHK(p, hipcub::DeviceRadixSort::SortKeys(temp, tb, kin, kout, (int)E, 0, std::min(end_bit + 1, 64), st));
+    HIPCHK(p, rocprim::radix_sort_keys(temp, tb, kin, kout, (int)E, 0, (unsigned)std::min(end_bit + 1, 64), st));
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks(N)), dim3(256), 0, st, rstart, N, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks(N)), dim3(256), 0, st, rend, N, 0);
     hipLaunchKernelGGL(k_tdeg, dim3(blocks(E)), dim3(256), 0, st, kout, E, N * ns, rstart, rend);
@@ -1571,9 +1581,9 @@ int build_halos(rbffd_plan* p, void* wsp, hipStream_t st) {
     hipLaunchKernelGGL(k_hkeys, dim3(blocks(E)), dim3(256), 0, st, o.st_union, N, (int)ns, tsz, kin);
     int end_bit = 32;
     while (end_bit < 64 && ((uint64_t)1 << (end_bit - 32)) <= (uint64_t)o.nwg) ++end_bit;
-    HIPCHK(p, hipcub::DeviceRadixSort::SortKeys(temp, tb, kin, kout, (int)E, 0, end_bit, st));
+    HIPCHK(p, rocprim::radix_sort_keys(temp, tb, kin, kout, (int)E, 0, (unsigned)end_bit, st));
     hipLaunchKernelGGL(k_hflags, dim3(blocks(E)), dim3(256), 0, st, kout, E, flag);
-    HIPCHK(p, hipcub::DeviceScan::ExclusiveSum(stemp, sb, flag, pos, (int)E, st));
+    HIPCHK(p, rocprim::exclusive_scan(stemp, sb, flag, pos, (int32_t)0, (size_t)E, rocprim::plus<int32_t>(), st));
     hipLaunchKernelGGL(k_hcompact, dim3(blocks(E)), dim3(256), 0, st, kout, flag, pos, E, o.hpool, o.hoff, o.nwg);
     hipLaunchKernelGGL(k_hlocal, dim3(blocks(o.tiles * RBFFD_TILE)), dim3(256), 0, st, o.st_union, N, (int)ns,
                        o.hpool, o.hoff, o.Q8, o.tiles, tsz, o.lidx);

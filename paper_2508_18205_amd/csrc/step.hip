@@ -19,10 +19,12 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
 #include "fields.h"
+#include "wpack.h"
 
 namespace {
 
@@ -109,6 +111,7 @@ template <typename TS, typename TW>
 __global__ __launch_bounds__(512) void k_h2(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
+    using WV = typename WF<TW>::V;
     const int64_t tile = tile_of(a);
     if (tile >= a.tiles) return;
     const int lane = threadIdx.x & 63;
@@ -119,16 +122,16 @@ __global__ __launch_bounds__(512) void k_h2(SA<TS, TW> a) {
     S::ld2(a.H, ic, hx0, hy0);
     TC dx = 0, dy = 0, vx = 0, vy = 0;
     const int4* pi = a.idx + tile * a.S4 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 2 * WF<TW>::CH + lane * WF<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * WF<TW>::CH + lane * WF<TW>::LS;
     const int qb = min(a.C4, a.V4);
     int q = 0;
     for (; q < qb; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
-        TW wx[4], wy[4], wh[4];
-        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
-        ldw4p(ph + q * RBFFD_TILE * 4, wh);
+        WV wx[4], wy[4], wh[4];
+        WF<TW>::ldp(pc + (q * 2 + 0) * WF<TW>::CH, wx);
+        WF<TW>::ldp(pc + (q * 2 + 1) * WF<TW>::CH, wy);
+        WF<TW>::ldp(ph + q * WF<TW>::CH, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int jj = idx4(j, u);
@@ -143,9 +146,9 @@ __global__ __launch_bounds__(512) void k_h2(SA<TS, TW> a) {
     }
     for (; q < a.C4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
-        TW wx[4], wy[4];
-        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+        WV wx[4], wy[4];
+        WF<TW>::ldp(pc + (q * 2 + 0) * WF<TW>::CH, wx);
+        WF<TW>::ldp(pc + (q * 2 + 1) * WF<TW>::CH, wy);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const TC de = S::ld1(a.E, idx4(j, u)) - e0;
@@ -155,8 +158,8 @@ __global__ __launch_bounds__(512) void k_h2(SA<TS, TW> a) {
     }
     for (; q < a.V4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
-        TW wh[4];
-        ldw4p(ph + q * RBFFD_TILE * 4, wh);
+        WV wh[4];
+        WF<TW>::ldp(ph + q * WF<TW>::CH, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             TC hx, hy;
@@ -186,6 +189,7 @@ template <typename TS, typename TW>
 __global__ __launch_bounds__(512) void k_e2(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
+    using WV = typename WF<TW>::V;
     const int64_t tile = tile_of(a);
     if (tile >= a.tiles) return;
     const int lane = threadIdx.x & 63;
@@ -196,16 +200,16 @@ __global__ __launch_bounds__(512) void k_e2(SA<TS, TW> a) {
     S::ld2(a.H, ic, hx0, hy0);
     TC cu = 0, ve = 0;
     const int4* pi = a.idx + tile * a.S4 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 2 * WF<TW>::CH + lane * WF<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * WF<TW>::CH + lane * WF<TW>::LS;
     const int qb = min(a.C4, a.V4);
     int q = 0;
     for (; q < qb; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
-        TW wx[4], wy[4], wh[4];
-        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
-        ldw4p(ph + q * RBFFD_TILE * 4, wh);
+        WV wx[4], wy[4], wh[4];
+        WF<TW>::ldp(pc + (q * 2 + 0) * WF<TW>::CH, wx);
+        WF<TW>::ldp(pc + (q * 2 + 1) * WF<TW>::CH, wy);
+        WF<TW>::ldp(ph + q * WF<TW>::CH, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int jj = idx4(j, u);
@@ -217,9 +221,9 @@ __global__ __launch_bounds__(512) void k_e2(SA<TS, TW> a) {
     }
     for (; q < a.C4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
-        TW wx[4], wy[4];
-        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+        WV wx[4], wy[4];
+        WF<TW>::ldp(pc + (q * 2 + 0) * WF<TW>::CH, wx);
+        WF<TW>::ldp(pc + (q * 2 + 1) * WF<TW>::CH, wy);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             TC hx, hy;
@@ -229,8 +233,8 @@ __global__ __launch_bounds__(512) void k_e2(SA<TS, TW> a) {
     }
     for (; q < a.V4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
-        TW wh[4];
-        ldw4p(ph + q * RBFFD_TILE * 4, wh);
+        WV wh[4];
+        WF<TW>::ldp(ph + q * WF<TW>::CH, wh);
 #pragma unroll
         for (int u = 0; u < 4; ++u) ve += (TC)wh[u] * (S::ld1(a.E, idx4(j, u)) - e0);
     }
@@ -356,6 +360,7 @@ template <typename TS, typename TW>
 __global__ __launch_bounds__(256) void k_h2s(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
+    using WV = typename WF<TW>::V;
     __shared__ TC part[3][4][RBFFD_TILE];
     const int64_t tile = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -366,15 +371,15 @@ __global__ __launch_bounds__(256) void k_h2s(SA<TS, TW> a) {
     S::ld2(a.H, ic, hx0, hy0);
     TC dx = 0, dy = 0, vx = 0, vy = 0;
     const int4* pi = a.idx + tile * a.S4 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 2 * WF<TW>::CH + lane * WF<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * WF<TW>::CH + lane * WF<TW>::LS;
     const int qm = max(a.C4, a.V4);
     for (int q = r; q < qm; q += 4) {
         const int4 j = pi[q * RBFFD_TILE];
         if (q < a.C4) {
-            TW wx[4], wy[4];
-            ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-            ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+            WV wx[4], wy[4];
+            WF<TW>::ldp(pc + (q * 2 + 0) * WF<TW>::CH, wx);
+            WF<TW>::ldp(pc + (q * 2 + 1) * WF<TW>::CH, wy);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const TC de = S::ld1(a.E, idx4(j, u)) - e0;
@@ -383,8 +388,8 @@ __global__ __launch_bounds__(256) void k_h2s(SA<TS, TW> a) {
             }
         }
         if (q < a.V4) {
-            TW wh[4];
-            ldw4p(ph + q * RBFFD_TILE * 4, wh);
+            WV wh[4];
+            WF<TW>::ldp(ph + q * WF<TW>::CH, wh);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 TC hx, hy;
@@ -422,6 +427,7 @@ template <typename TS, typename TW>
 __global__ __launch_bounds__(256) void k_e2s(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
+    using WV = typename WF<TW>::V;
     __shared__ TC part[3][2][RBFFD_TILE];
     const int64_t tile = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -432,15 +438,15 @@ __global__ __launch_bounds__(256) void k_e2s(SA<TS, TW> a) {
     S::ld2(a.H, ic, hx0, hy0);
     TC cu = 0, ve = 0;
     const int4* pi = a.idx + tile * a.S4 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 2 * WF<TW>::CH + lane * WF<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * WF<TW>::CH + lane * WF<TW>::LS;
     const int qm = max(a.C4, a.V4);
     for (int q = r; q < qm; q += 4) {
         const int4 j = pi[q * RBFFD_TILE];
         if (q < a.C4) {
-            TW wx[4], wy[4];
-            ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
-            ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+            WV wx[4], wy[4];
+            WF<TW>::ldp(pc + (q * 2 + 0) * WF<TW>::CH, wx);
+            WF<TW>::ldp(pc + (q * 2 + 1) * WF<TW>::CH, wy);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 TC hx, hy;
@@ -449,8 +455,8 @@ __global__ __launch_bounds__(256) void k_e2s(SA<TS, TW> a) {
             }
         }
         if (q < a.V4) {
-            TW wh[4];
-            ldw4p(ph + q * RBFFD_TILE * 4, wh);
+            WV wh[4];
+            WF<TW>::ldp(ph + q * WF<TW>::CH, wh);
 #pragma unroll
             for (int u = 0; u < 4; ++u) ve += (TC)wh[u] * (S::ld1(a.E, idx4(j, u)) - e0);
         }
@@ -646,14 +652,14 @@ __device__ __forceinline__ void copy4(TW (&d)[4], const TW (&s)[4]) {
     d[3] = s[3];
 }
 // weights of chunk q of a 2D block (left unchanged past the chunk counts)
-template <typename TW>
-__device__ __forceinline__ void load2(const TW* pc, const TW* ph, int q, int C4, int V4, TW (&x)[4], TW (&y)[4],
-                                      TW (&h)[4]) {
+template <typename TW, typename WV = typename WF<TW>::V>
+__device__ __forceinline__ void load2(const TW* pc, const TW* ph, int q, int C4, int V4, WV (&x)[4], WV (&y)[4],
+                                      WV (&h)[4]) {
     if (q < C4) {
-        ldw4(pc + (q * 2 + 0) * RBFFD_TILE * 4, x);
-        ldw4(pc + (q * 2 + 1) * RBFFD_TILE * 4, y);
+        WF<TW>::ld(pc + (q * 2 + 0) * WF<TW>::CH, x);
+        WF<TW>::ld(pc + (q * 2 + 1) * WF<TW>::CH, y);
     }
-    if (q < V4) ldw4(ph + q * RBFFD_TILE * 4, h);
+    if (q < V4) WF<TW>::ld(ph + q * WF<TW>::CH, h);
 }
 
 // weights of chunk q of a 3D block (left unchanged past the chunk counts)
@@ -762,6 +768,7 @@ template <typename TS, typename TW>
 __global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
+    using WV = typename WF<TW>::V;
     TC* sE = lds_base<TC>();
     TC* sH = sE + ((a.hmax + 3) & ~3);                 // pairs (Hx, Hy)
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -789,16 +796,16 @@ __global__ __launch_bounds__(256) void k_h2l(SA<TS, TW> a) {
     S::ld2(a.H, ic, hx0, hy0);
     TC dx = 0, dy = 0, vx = 0, vy = 0;
     const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 2 * WF<TW>::CH + lane * WF<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * WF<TW>::CH + lane * WF<TW>::LS;
     const int qm = max(a.C4, a.V4);
     // chunk q + 1 is loaded while chunk q is summed
     uint4 li = ldu4s(pl);
-    TW nx[4] = {0, 0, 0, 0}, ny[4] = {0, 0, 0, 0}, nh[4] = {0, 0, 0, 0};
+    WV nx[4] = {0, 0, 0, 0}, ny[4] = {0, 0, 0, 0}, nh[4] = {0, 0, 0, 0};
     load2(pc, ph, 0, a.C4, a.V4, nx, ny, nh);
     for (int q = 0; q < qm; ++q) {
         const uint4 lc = li;
-        TW wx[4], wy[4], wh[4];
+        WV wx[4], wy[4], wh[4];
         copy4(wx, nx); copy4(wy, ny); copy4(wh, nh);
         if (q + 1 < qm) {
             if (((q + 1) & 1) == 0) li = ldu4s(pl + ((q + 1) >> 1) * RBFFD_TILE);
@@ -844,6 +851,7 @@ template <typename TS, typename TW>
 __global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
+    using WV = typename WF<TW>::V;
     TC* sE = lds_base<TC>();
     TC* sH = sE + ((a.hmax + 3) & ~3);
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -871,15 +879,15 @@ __global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
     S::ld2(a.H, ic, hx0, hy0);
     TC cu = 0, ve = 0;
     const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 2 * WF<TW>::CH + lane * WF<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * WF<TW>::CH + lane * WF<TW>::LS;
     const int qm = max(a.C4, a.V4);
     uint4 li = ldu4s(pl);
-    TW nx[4] = {0, 0, 0, 0}, ny[4] = {0, 0, 0, 0}, nh[4] = {0, 0, 0, 0};
+    WV nx[4] = {0, 0, 0, 0}, ny[4] = {0, 0, 0, 0}, nh[4] = {0, 0, 0, 0};
     load2(pc, ph, 0, a.C4, a.V4, nx, ny, nh);
     for (int q = 0; q < qm; ++q) {
         const uint4 lc = li;
-        TW wx[4], wy[4], wh[4];
+        WV wx[4], wy[4], wh[4];
         copy4(wx, nx); copy4(wy, ny); copy4(wh, nh);
         if (q + 1 < qm) {
             if (((q + 1) & 1) == 0) li = ldu4s(pl + ((q + 1) >> 1) * RBFFD_TILE);
@@ -1409,6 +1417,8 @@ void fill_sa(const rbffd_plan* p, const OpBlock& o, SA<TS, TW>& a, bool hupd) {
 template <typename TS, typename TW>
 void launch_half(const rbffd_plan* p, bool hupd, const void* E, const void* H, void* out, const void* eps_r,
                  hipStream_t st) {
+    // compressed (W22) weights exist only for the 2D collocated kernels
+    constexpr bool kW22 = std::is_same<TW, w22>::value;
     const OpBlock& o = hupd ? p->opH : p->opE;
     SA<TS, TW> a{};
     fill_sa(p, o, a, hupd);
@@ -1435,6 +1445,11 @@ void launch_half(const rbffd_plan* p, bool hupd, const void* E, const void* H, v
             const size_t lds = (size_t)(((o.hmax + 3) & ~3) + 2 * o.hmax) * sizeof(TC);
             if (hupd) hipLaunchKernelGGL((k_h2l<TS, TW>), grid, block, lds, st, a);
             else hipLaunchKernelGGL((k_e2l<TS, TW>), grid, block, lds, st, a);
+            return;
+        }
+        if constexpr (kW22) {
+            // compressed weights: 2D collocated plans only (refused at plan creation otherwise)
+            return;
         } else if (o.stage == 1 && p->var.lds != 2) {
             const size_t lds = (size_t)6 * o.hmax * sizeof(TC);
             if (hupd) hipLaunchKernelGGL((k_h3l<TS, TW>), grid, block, lds, st, a);
@@ -1454,24 +1469,29 @@ void launch_half(const rbffd_plan* p, bool hupd, const void* E, const void* H, v
     }
     const int wpb = p->var.block / 64;
     const dim3 grid((unsigned)cdiv(o.tiles, wpb)), block(p->var.block);
-    if (p->dim == 2) {
-        if (p->collocated) {
-            if (hupd) hipLaunchKernelGGL((k_h2<TS, TW>), grid, block, 0, st, a);
-            else hipLaunchKernelGGL((k_e2<TS, TW>), grid, block, 0, st, a);
-        } else {
+    if (p->dim == 2 && p->collocated) {
+        if (hupd) hipLaunchKernelGGL((k_h2<TS, TW>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_e2<TS, TW>), grid, block, 0, st, a);
+        return;
+    }
+    if constexpr (!kW22) {
+        if (p->dim == 2) {
             if (hupd) hipLaunchKernelGGL((k_h2x<TS, TW>), grid, block, 0, st, a);
             else hipLaunchKernelGGL((k_e2x<TS, TW>), grid, block, 0, st, a);
+        } else {
+            if (hupd) hipLaunchKernelGGL((k_h3<TS, TW>), grid, block, 0, st, a);
+            else hipLaunchKernelGGL((k_e3<TS, TW>), grid, block, 0, st, a);
         }
-    } else {
-        if (hupd) hipLaunchKernelGGL((k_h3<TS, TW>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_e3<TS, TW>), grid, block, 0, st, a);
     }
 }
 
 void half(const rbffd_plan* p, bool hupd, const void* E, const void* H, void* out, const void* eps_r, hipStream_t st) {
     switch (p->p.fdtype) {
         case RBFFD_F64: launch_half<double, double>(p, hupd, E, H, out, eps_r, st); break;
-        case RBFFD_F32: launch_half<float, float>(p, hupd, E, H, out, eps_r, st); break;
+        case RBFFD_F32:
+            if (p->p.wdtype == RBFFD_W22) launch_half<float, w22>(p, hupd, E, H, out, eps_r, st);
+            else launch_half<float, float>(p, hupd, E, H, out, eps_r, st);
+            break;
         default: launch_half<bf16s, float>(p, hupd, E, H, out, eps_r, st); break;
     }
 }
@@ -1619,20 +1639,10 @@ extern "C" int rbffd_run(const rbffd_plan* p, rbffd_fields* f, const rbffd_run_a
     RunWS w = run_ws(ws);
     hipLaunchKernelGGL(k_ctr_set, dim3(1), dim3(64), 0, st, w.ctr, 0);
     int s = 0;
-    if (a->use_graph && a->T >= 4) {
-        // capture two steps (c -> o -> c) and replay; buffers return to their roles
-        hipGraph_t g;
-        hipGraphExec_t ge;
-        hipStream_t cs;
-        if ((rc = capture_stream(p, &cs))) return rc;
-        HIPCHK(p, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        full_step(p, f, f->cur, a, w, cs);
-        full_step(p, f, 1 - f->cur, a, w, cs);
-        HIPCHK(p, hipStreamEndCapture(cs, &g));
-        HIPCHK(p, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-        for (; s + 2 <= a->T; s += 2) HIPCHK(p, hipGraphLaunch(ge, st));
-        HIPCHK(p, hipGraphExecDestroy(ge));
-        HIPCHK(p, hipGraphDestroy(g));
+    if (a->use_graph) {
+        rc = replay_steps(
+            p, a->T, f->cur, st, [&](int c, hipStream_t cs) { full_step(p, f, c, a, w, cs); }, &s);
+        if (rc) return rc;
     }
     int c = f->cur;
     if (s > 0 && (s % 2)) c = 1 - c;

@@ -54,7 +54,7 @@ class Solver:
     def __init__(self, dim, xyz, flags, h, n, m, alpha, hv_c, lo, hi, *, n_hv=0, dt=0.0, mode="FD",
                  bc="PEC", eps0=1.0, mu0=1.0, vfd_sigma=0.5, phs_k=3, precision="f64", K=1,
                  adjoint=False, reorder="MORTON", xyz_h=None, flags_h=None, h_h=0.0, pol="TM", frame_angle=0.0,
-                 normals=None, device="cuda:0"):
+                 normals=None, weights=None, device="cuda:0"):
         self.lib = _abi.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the rbffd library needs a GPU (no CPU path)")
@@ -65,7 +65,9 @@ class Solver:
         p = _abi.Params()
         p.dim, p.mode, p.n, p.m, p.phs_k = dim, _abi.MODE[mode], n, m, phs_k
         p.hv_alpha, p.n_hv, p.bc, p.reorder = alpha, n_hv, _abi.BC[bc], _abi.ORDER[reorder]
-        p.wdtype = 0 if precision == "f64" else 1
+        # weight storage: FP64 with FP64 fields, else FP32, or "w22" (compressed
+        # FP32 weights: 22-bit mantissas, one exponent per 4-slot chunk)
+        p.wdtype = 0 if precision == "f64" else (_abi.W22 if weights == "w22" else 1)
         p.fdtype = _abi.DTYPE[precision]
         p.K, p.adjoint = K, int(bool(adjoint))
         p.pol = {"TM": 0, "TE": 1}[pol]

@@ -99,13 +99,20 @@ def test_plan_validation_and_sizes_on_host():
                       (dict(pol=1, adjoint=1), _abi.ENOTSUP), (dict(pol=1, mode=2), _abi.ENOTSUP),
                       # rotated frame: 2D only, finite, not with axis-aligned TEz walls
                       (dict(frame_angle=float("nan")), _abi.EINVAL),
-                      (dict(pol=1, frame_angle=0.3), _abi.ENOTSUP)):
+                      (dict(pol=1, frame_angle=0.3), _abi.ENOTSUP),
+                      # weight storage must match the fields; compressed (W22)
+                      # weights: 2D collocated single-field FP32 only
+                      (dict(wdtype=1, fdtype=0), _abi.EINVAL), (dict(wdtype=0, fdtype=1), _abi.EINVAL),
+                      (dict(wdtype=3), _abi.ENOTSUP), (dict(wdtype=3, fdtype=1, K=4), _abi.ENOTSUP),
+                      (dict(wdtype=3, fdtype=1, adjoint=1), _abi.ENOTSUP),
+                      (dict(wdtype=3, fdtype=2), _abi.ENOTSUP), (dict(wdtype=4, fdtype=1), _abi.EINVAL)):
         p = _params(_abi, **bad)
         rc = lib.rbffd_plan_create(C.byref(p), xyz.shape[0], xyz.ctypes.data, flags.ctypes.data, 0, None, None,
                                    C.byref(plan))
         assert rc == code, bad
     nowall = np.zeros_like(flags)
-    for good in (dict(frame_angle=0.3, mode=1), dict(frame_angle=-0.7, pol=1, bc=1)):
+    for good in (dict(frame_angle=0.3, mode=1), dict(frame_angle=-0.7, pol=1, bc=1), dict(wdtype=3, fdtype=1),
+                 dict(wdtype=3, fdtype=1, pol=1, mode=1)):
         p = _params(_abi, **good)
         fl = nowall if good.get("bc") == 1 else flags
         if good.get("bc") == 1:

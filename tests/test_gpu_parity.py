@@ -770,3 +770,57 @@ def test_well_conditioned_neighbours_of_the_floor_still_solve():
     dx = (wc[:, 0, :] * (X[st, 0] - X[:, None, 0])).sum(1)
     dy = (wc[:, 1, :] * (X[st, 1] - X[:, None, 1])).sum(1)
     assert np.abs(dx - 1.0).max() < 1e-6 and np.abs(dy - 1.0).max() < 1e-6
+
+
+@pytest.mark.parametrize("T", [151, 64, 5])
+def test_graph_loop_of_many_steps_equals_eager(T):
+    # the run replays graphs of up to 64 captured steps, then a graph of the
+    # remaining step pairs, then the last odd step eagerly: fields, energy
+    # samples, traces and checkpoints equal the eager run bit for bit
+    _announce(f"graph loop of {T} steps vs eager")
+    w = configs.adjoint_2d(n_side=30, steps=T, chat=1e-3)
+    s = Solver.from_workload(w, precision="f64")
+    src = (w.src_node, w.src_amp, w.src_wave)
+    outs = []
+    for g in (False, True):
+        st = s.state(w.E0, w.H0, eps_r=w.eps_r)
+        out = s.run(st, T, energy_every=7, src=src, rcv=w.rcv_node, ckpt_every=13, use_graph=g)
+        outs.append((s.E_original(st), s.H_original(st), out["energy"], out["traces"].cpu().numpy(),
+                     out["ckpt"].cpu().numpy(), st.cur))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_compressed_w22_weights_against_the_oracle(pol):
+    # FP32 fields with W22 weights (22-bit mantissas, one exponent per 4-slot
+    # chunk): the cavity mode over 1 1/8 periods against the FP64 oracle
+    # within the FP32 bar, and close to the FP32-weight plan; the staged and
+    # global kernels agree bit for bit (same arithmetic, same order) and the
+    # four-wavefront small-set kernels to rounding
+    _announce(f"W22 weights, {pol} cavity")
+    make = configs.tm_cavity_2d if pol == "TM" else configs.te_cavity_2d
+    w = make(n_side=51, chat=1e-3, eps0=2.0, mu0=0.5)
+    w.steps = int(round(1.125 * w.steps))
+    oh, oe = osetup.operators(w)
+    Eo, Ho, _, _ = osetup.run_workload(w, oh, oe)
+    s32 = Solver.from_workload(w, precision="f32")
+    st = s32.state(w.E0, w.H0)
+    s32.step(st, w.steps)
+    E32, H32 = s32.E_original(st), s32.H_original(st)
+    s = Solver.from_workload(w, precision="f32", weights="w22")
+    assert np.array_equal(s.weights(_abi.OP_CURL_H), s32.weights(_abi.OP_CURL_H))
+    out = []
+    for lds in (1, 0, 3):
+        s.set_variant(block=256, xcd=1, lds=lds)
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        out.append((s.E_original(st), s.H_original(st)))
+    E, H = out[0]
+    eE, eH = ostep.rel_l2(E, Eo), ostep.rel_l2(H, Ho)
+    dE, dH = ostep.rel_l2(E, E32), ostep.rel_l2(H, H32)
+    _announce(f"  vs oracle E {eE:.2e} H {eH:.2e}; vs FP32 weights E {dE:.2e} H {dH:.2e}")
+    assert eE < 1e-5 and eH < 1e-5
+    assert dE < 5e-6 and dH < 5e-6 and (dE > 0 or dH > 0)
+    assert np.array_equal(out[1][0], E) and np.array_equal(out[1][1], H)
+    assert ostep.rel_l2(out[2][0], E) < 1e-6 and ostep.rel_l2(out[2][1], H) < 1e-6
