@@ -90,19 +90,20 @@ def dispersion_l1(samples, every, jmax=45):
 
 
 def counted_traffic(kernel):
-    """HBM bytes per launch of ``kernel`` from the committed counter summary.
-
-    Returns None unless the step-kernel source is the one the counters were
-    taken on (sha256 prefix recorded in the summary).
-    """
+    """HBM bytes per launch of ``kernel`` (e.g. "k_h2l<float,float>") from the
+    committed counter summary: FETCH_SIZE and WRITE_SIZE, each scaled by what
+    the same counter reads for the 2 GiB copy probe (the per-size request
+    counts give the same bytes to 0.01 %).  None unless the step-kernel
+    sources are the ones the counters were taken on (hash in the summary)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_pulse2d_1M_f32.md")
-    src = os.path.join(ROOT, "paper_2508_18205_amd", "csrc", "step.hip")
+    path = os.path.join(ROOT, "profiles", "traffic_pulse2d_1M.md")
     if not os.path.exists(path):
         return None
+    h = hashlib.sha256()
+    for f in ("step.hip", "common.h", "fields.h", "wpack.h"):
+        h.update(open(os.path.join(ROOT, "paper_2508_18205_amd", "csrc", f), "rb").read())
     text = open(path).read()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if f"sha256 prefix at measurement: {sha}" not in text:
+    if f"(step.hip, common.h, fields.h, wpack.h): {h.hexdigest()[:16]}" not in text:
         return None
     for line in text.splitlines():
         if line.startswith(f"traffic_bytes_per_launch {kernel}:"):
@@ -199,6 +200,57 @@ def vs_oracle(s, st, energy, g):
             "whole_field_rel_l2_E_est": prel(pE, g["projE"]), "whole_field_rel_l2_H_est": prel(pH, g["projH"])}
 
 
+def kernels_only(args):
+    """Average duration of each half-update kernel of the named plans, with
+    the same autotuned variant the benchmark uses, from rbffd_half launches
+    alone (no graph replay): the process runs only the set-up, the tuner and
+    these launches, for per-kernel profiler counters."""
+    import torch
+    from synth import configs
+    from paper_2508_18205_amd import Solver
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    out = {}
+    for name in args.kernels.split(","):
+        if name == "copy":
+            # the streaming copy probe: 10 copies of 2 GiB
+            import ctypes as _ct
+            from paper_2508_18205_amd import _abi as _ab
+            lib = _ab.load()
+            ca = torch.ones(1 << 29, dtype=torch.float32, device="cuda:0")
+            cb = torch.empty_like(ca)
+            sp = _ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                _ab.check(lib.rbffd_stream_copy(_ct.c_void_p(ca.data_ptr()), _ct.c_void_p(cb.data_ptr()),
+                                                ca.numel() * 4, sp))
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / 10
+            out[name] = {"bytes_each_way": ca.numel() * 4, "avg_us": round(us, 2),
+                         "GBs": round(2 * ca.numel() * 4 / (us * 1e-6) / 1e9, 1)}
+            log(f"copy: {out[name]}")
+            del ca, cb
+            torch.cuda.empty_cache()
+            continue
+        wl, _, prec = name.partition("_")
+        w = configs.pulse_2d(scale=args.scale) if wl == "pulse2d" else configs.tm111_3d(scale=args.scale, chat=1e-3)
+        kw = {"weights": "w22"} if prec == "w22" else {}
+        s = Solver.from_workload(w, precision="f32" if prec == "w22" else prec, **kw)
+        st = s.state(w.E0, w.H0)
+        if not args.no_tune:
+            s.autotune(st, reps=3)
+            st = s.state(w.E0, w.H0)
+        th, te = time_halves(s, st, args.kernel_reps, torch)
+        out[name] = {"N": w.N, "h_update_us": round(th * 1e6, 2), "e_update_us": round(te * 1e6, 2),
+                     "variant": s.variant()}
+        log(f"{name}: {out[name]}")
+        del s, st
+        torch.cuda.empty_cache()
+    print(json.dumps({"kernels": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +265,11 @@ def main():
     ap.add_argument("--legs", default="fp64,accuracy,alpha2,w22,cavity,batched,bf16,adjoint,stag2,hv_scan,dispersion,disk,te,3d",
                     help="comma-separated extra legs to run after the headline measurement")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--kernels", default=None,
+                    help="profiling mode: only time the half-step kernels, launched one by one (no graph replay), "
+                         "for a comma-separated list of pulse2d_f32, pulse2d_f64, pulse2d_w22, cube3d_f32, "
+                         "cube3d_f64 (and copy: the 2 GiB streaming copy probe); prints one JSON line of average "
+                         "launch times")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library has no multi-GPU path "
@@ -224,6 +281,8 @@ def main():
     from synth import configs
     from paper_2508_18205_amd import Solver
 
+    if args.kernels:
+        return kernels_only(args)
     t0 = time.time()
     w = configs.pulse_2d(scale=args.scale)
     t_gen = time.time() - t0
@@ -308,10 +367,10 @@ def main():
     kname = ("k_h2l" if dominant == "H" else "k_e2l") if staged else ("k_h2" if dominant == "H" else "k_e2")
     traffic = None
     if staged and args.precision == "f32" and args.scale == 1.0:
-        traffic = counted_traffic(kname)
+        traffic = counted_traffic(kname + "<float,float>")
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by the same counter read for the 2 GiB stream copy)",
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by the same counter read for the 2 GiB stream copy; profiles/traffic_pulse2d_1M.md)",
             "kernel": f"{kname}<float,float> ({'H' if dominant == 'H' else 'E'} update)",
             "alg_bytes_per_launch": int(bh if dominant == "H" else be),
             "avg_launch_us": round((th if dominant == "H" else te) * 1e6, 2),
@@ -436,6 +495,10 @@ def main():
                "h_update_us": round(th22 * 1e6, 2), "e_update_us": round(te22 * 1e6, 2),
                "h_update_GBs": round(bh22 / th22 / 1e9, 1), "e_update_GBs": round(be22 / te22 / 1e9, 1),
                "h_update_frac": round(bh22 / th22 / 1e9 / HBM_PEAK_GBS, 4)}
+        t22 = counted_traffic("k_h2l<float,w22>")
+        if t22:
+            leg["h_update_traffic"] = t22
+            leg["h_update_counted_GBs"] = round(t22 / th22 / 1e9, 1)
         g3 = golden("a3")
         if g3 is not None:
             leg["vs_oracle_configured"] = oracle_run(sw, w, g3)
