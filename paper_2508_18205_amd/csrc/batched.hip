@@ -118,9 +118,10 @@ __global__ __launch_bounds__(256) void k_eb(BA a) {
 }
 
 // ---- LDS-staged batch -----------------------------------------------------
-// Workgroup = one 256-node tile x one 16-field slice (1024 threads).  It
-// copies the slice of every halo node's rows (E, Hx, Hy) into LDS, then 4
-// threads per node each update 4 fields; stencil positions (16-bit) and
+// Workgroup = one 128-node tile x one 16-field slice (512 threads; the halo
+// slice takes ~60 KB of LDS, so two workgroups share a CU and one stages
+// while the other sums).  It copies the slice of every halo node's rows (E,
+// Hx, Hy) into LDS, then 4 threads per node each update 4 fields; stencil positions (16-bit) and
 // weights come from the same tile-sliced packed arrays as the single-field
 // kernels (and the same halo lists), one 16-byte load per 4 slots shared by
 // the node's 4 threads.  The slices of one tile are consecutive workgroups,
@@ -221,18 +222,23 @@ __device__ __forceinline__ const float* row(const float* sm, int k, int c, int f
     return sm + (k * 3 + c) * KSL + fq * 4;
 }
 
+// the weights of chunk q (left as they are past the chunk counts)
+__device__ __forceinline__ void w_read(const BLA& a, int q, const float* pc, const float* ph, f4& wx, f4& wy, f4& wh) {
+    if (q < a.C4) {
+        wx = ldf4(pc + (q * 2 + 0) * RBFFD_TILE * 4);
+        wy = ldf4(pc + (q * 2 + 1) * RBFFD_TILE * 4);
+    }
+    if (q < a.V4) wh = ldf4(ph + q * RBFFD_TILE * 4);
+}
+
 template <int KSL>
-__device__ __forceinline__ void h_read(const BLA& a, const float* sm, uint4 lp, int q, int fq, const float* pc,
-                                       const float* ph, HChunk& c) {
+__device__ __forceinline__ void h_read(const BLA& a, const float* sm, uint4 lp, int q, int fq, HChunk& c) {
     const int hf = q & 1;
     if (q < a.C4) {
-        c.wx = ldf4(pc + (q * 2 + 0) * RBFFD_TILE * 4);
-        c.wy = ldf4(pc + (q * 2 + 1) * RBFFD_TILE * 4);
 #pragma unroll
         for (int u = 0; u < 4; ++u) c.e[u] = ldf4(row<KSL>(sm, posq(lp, hf, u), 0, fq));
     }
     if (q < a.V4) {
-        c.wh = ldf4(ph + q * RBFFD_TILE * 4);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int k = posq(lp, hf, u);
@@ -263,12 +269,9 @@ __device__ __forceinline__ void h_sum(const BLA& a, int q, const HChunk& c, cons
 }
 
 template <int KSL>
-__device__ __forceinline__ void e_read(const BLA& a, const float* sm, uint4 lp, int q, int fq, const float* pc,
-                                       const float* ph, EChunk& c) {
+__device__ __forceinline__ void e_read(const BLA& a, const float* sm, uint4 lp, int q, int fq, EChunk& c) {
     const int hf = q & 1;
     if (q < a.C4) {
-        c.wx = ldf4(pc + (q * 2 + 0) * RBFFD_TILE * 4);
-        c.wy = ldf4(pc + (q * 2 + 1) * RBFFD_TILE * 4);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int k = posq(lp, hf, u);
@@ -277,7 +280,6 @@ __device__ __forceinline__ void e_read(const BLA& a, const float* sm, uint4 lp, 
         }
     }
     if (q < a.V4) {
-        c.wh = ldf4(ph + q * RBFFD_TILE * 4);
 #pragma unroll
         for (int u = 0; u < 4; ++u) c.e[u] = ldf4(row<KSL>(sm, posq(lp, hf, u), 0, fq));
     }
@@ -311,7 +313,7 @@ __device__ __forceinline__ uint4 pair_pos(const uint4* pl, int m, int npairs) {
 }
 
 template <int TPN>
-__global__ __launch_bounds__(RBFFD_WGT * TPN) void k_hbl(BLA a) {
+__global__ __launch_bounds__(RBFFD_WGT_BATCH * TPN) void k_hbl(BLA a) {
     constexpr int KSL = 4 * TPN;          // fields per slice, 4 per thread
     extern __shared__ __align__(16) float sm[];
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(RBFFD_WGT * TPN) void k_hbl(BLA a) {
     stage_slice<KSL>(a, sm, tile, ks);
     __syncthreads();
     const int nl = threadIdx.x / TPN, fq = threadIdx.x % TPN;
-    const int64_t i = tile * RBFFD_WGT + nl;
+    const int64_t i = tile * RBFFD_WGT_BATCH + nl;
     if (i >= a.N) return;
     const int64_t t64 = i / RBFFD_TILE;
     const int ln = (int)(i % RBFFD_TILE);
@@ -333,11 +335,22 @@ __global__ __launch_bounds__(RBFFD_WGT * TPN) void k_hbl(BLA a) {
     const float* ph = a.wh + (t64 * a.V4 * RBFFD_TILE + ln) * 4;
     const int qm = max(a.C4, a.V4);
     const int np = (qm + 1) >> 1;
-    uint4 lp = make_uint4(0, 0, 0, 0);
+    // the weights and halo positions of chunk q + 1 are loaded while chunk q
+    // is read from LDS and summed
+    uint4 lp = pair_pos(pl, 0, np), lpn = pair_pos(pl, 1, np);
     HChunk A;
+    f4 nx{0, 0, 0, 0}, ny{0, 0, 0, 0}, nh{0, 0, 0, 0};
+    w_read(a, 0, pc, ph, nx, ny, nh);
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) lp = pair_pos(pl, q >> 1, np);
-        h_read<KSL>(a, sm, lp, q, fq, pc, ph, A);
+        A.wx = nx;
+        A.wy = ny;
+        A.wh = nh;
+        if (q > 0 && (q & 1) == 0) {            // chunks 2m, 2m + 1 use pair m
+            lp = lpn;
+            lpn = pair_pos(pl, (q >> 1) + 1, np);
+        }
+        if (q + 1 < qm) w_read(a, q + 1, pc, ph, nx, ny, nh);
+        h_read<KSL>(a, sm, lp, q, fq, A);
         h_sum(a, q, A, e0, hx0, hy0, dx, dy, vx, vy);
     }
     const float Af = a.a;
@@ -349,7 +362,7 @@ __global__ __launch_bounds__(RBFFD_WGT * TPN) void k_hbl(BLA a) {
 }
 
 template <int TPN>
-__global__ __launch_bounds__(RBFFD_WGT * TPN) void k_ebl(BLA a) {
+__global__ __launch_bounds__(RBFFD_WGT_BATCH * TPN) void k_ebl(BLA a) {
     constexpr int KSL = 4 * TPN;          // fields per slice, 4 per thread
     extern __shared__ __align__(16) float sm[];
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -358,7 +371,7 @@ __global__ __launch_bounds__(RBFFD_WGT * TPN) void k_ebl(BLA a) {
     stage_slice<KSL>(a, sm, tile, ks);
     __syncthreads();
     const int nl = threadIdx.x / TPN, fq = threadIdx.x % TPN;
-    const int64_t i = tile * RBFFD_WGT + nl;
+    const int64_t i = tile * RBFFD_WGT_BATCH + nl;
     if (i >= a.N) return;
     const int64_t t64 = i / RBFFD_TILE;
     const int ln = (int)(i % RBFFD_TILE);
@@ -371,11 +384,20 @@ __global__ __launch_bounds__(RBFFD_WGT * TPN) void k_ebl(BLA a) {
     const float* ph = a.wh + (t64 * a.V4 * RBFFD_TILE + ln) * 4;
     const int qm = max(a.C4, a.V4);
     const int np = (qm + 1) >> 1;
-    uint4 lp = make_uint4(0, 0, 0, 0);
+    uint4 lp = pair_pos(pl, 0, np), lpn = pair_pos(pl, 1, np);
     EChunk A;
+    f4 nx{0, 0, 0, 0}, ny{0, 0, 0, 0}, nh{0, 0, 0, 0};
+    w_read(a, 0, pc, ph, nx, ny, nh);
     for (int q = 0; q < qm; ++q) {
-        if ((q & 1) == 0) lp = pair_pos(pl, q >> 1, np);
-        e_read<KSL>(a, sm, lp, q, fq, pc, ph, A);
+        A.wx = nx;
+        A.wy = ny;
+        A.wh = nh;
+        if (q > 0 && (q & 1) == 0) {            // chunks 2m, 2m + 1 use pair m
+            lp = lpn;
+            lpn = pair_pos(pl, (q >> 1) + 1, np);
+        }
+        if (q + 1 < qm) w_read(a, q + 1, pc, ph, nx, ny, nh);
+        e_read<KSL>(a, sm, lp, q, fq, A);
         e_sum(a, q, A, e0, hx0, hy0, cu, ve);
     }
     const float Af = a.a;
@@ -442,7 +464,7 @@ void launch_half_staged(const rbffd_plan* p, const rbffd_fields* f, int c, bool 
     a.xcd = p->var.xcd;
     a.gk = p->gk;
     a.emask = p->E.emask;
-    const dim3 grid((unsigned)(ob.nwg * a.KS)), block(RBFFD_WGT * tpn);
+    const dim3 grid((unsigned)(ob.nwg * a.KS)), block(RBFFD_WGT_BATCH * tpn);
     const size_t lds = (size_t)ob.hmax * 3 * ksl * sizeof(float);
     a.E = (const float*)f->E[c];
     if (hupd) {

@@ -14,6 +14,7 @@
 #define RBFFD_MAX_MONO 64         // monomials per local system
 #define RBFFD_TILE 64             // nodes per packed tile (one wavefront)
 #define RBFFD_WGT 256             // nodes per LDS-staged workgroup tile (4 wavefronts)
+#define RBFFD_WGT_BATCH 128       // K-field batch: nodes per staged tile (two workgroups share a CU)
 #define RBFFD_LDS_BUDGET 65536    // bytes of LDS one staged workgroup may use
 #define RBFFD_LDS_BUDGET_3D 98304 // 3D: both operands together up to this size (fewer
                                   // resident workgroups; the tuner also tries one at a time)
@@ -61,6 +62,7 @@ struct OpBlock {
     int32_t* hoff = nullptr;       // [nwg + 1] start of each workgroup's list
     int32_t Q8 = 0;
     int64_t nwg = 0;
+    int32_t wgt = RBFFD_WGT;       // nodes per staged workgroup tile (halo lists)
     int32_t hmax = 0;              // longest halo list (0 = staging unavailable)
     int32_t stage = 0;             // single field: 1 = both operands staged together,
                                    // 2 = one operand at a time (3D), 0 = none

@@ -1577,7 +1577,7 @@ int build_halos(rbffd_plan* p, void* wsp, hipStream_t st) {
     void* temp = w.take<char>((int64_t)tb);
     void* stemp = w.take<char>((int64_t)sb);
     const bool batch = p->K > 1;
-    const int tsz = RBFFD_WGT;
+    const int tsz = o.wgt;
     hipLaunchKernelGGL(k_hkeys, dim3(blocks(E)), dim3(256), 0, st, o.st_union, N, (int)ns, tsz, kin);
     int end_bit = 32;
     while (end_bit < 64 && ((uint64_t)1 << (end_bit - 32)) <= (uint64_t)o.nwg) ++end_bit;
