@@ -1,0 +1,125 @@
+"""Multi-step parity with the FP64 oracle at full size, in the launch
+configuration the benchmark times (autotuned variant, HIP-graph replay).
+
+* The 1.0M-node pulse (PEC unit square, n = 25, m = 4), end to end (the
+  GPU's own set-up and weights) in FP64 and FP32, against the oracle's FP64
+  run written by tests/golden/make_fullsize_golden.py:
+    - as configured (alpha = 3, n_hv = 57), 2000 steps;
+    - alpha = 2 (n_hv = 31, chat = 3e-3), 10^4 steps.
+  Checked: E and H at the stored sampled nodes (relative L2 over the sample,
+  per component), the energy of eq. 20 every 100 steps (a sum over every
+  node), and 8 seeded random projections of each full field component, whose
+  differences estimate the relative L2 difference of the whole field.
+  Bars: 1e-9 in FP64 (the two sides' weights differ by rounding of their
+  own FP64 solves), 1e-5 in FP32, with FP32 weights and with the compressed
+  W22 weights.
+* The two-set variant at the 2D cavity's size (51^2 E nodes, 50^2 H nodes,
+  TM_11, one period = 1000 steps), FP64 with injected oracle weights
+  (1e-12) and end to end (1e-9), against the oracle run in the test.
+"""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2508_18205_amd import Solver, _abi  # noqa: E402
+from oracle import setup as osetup, step as ostep  # noqa: E402
+from synth import configs  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _announce(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pulse():
+    return configs.pulse_2d(scale=1.0)
+
+
+def _workload(w, tag, g):
+    if tag == "a3":
+        assert (w.alpha, w.n_hv, w.chat) == (int(g["alpha"]), int(g["n_hv"]), float(g["chat"]))
+        return w
+    ws = configs.Workload(w.name, w.dim, w.xyz, w.flags, w.h, w.n, w.m, int(g["alpha"]), int(g["n_hv"]),
+                          float(g["chat"]), int(g["steps"]))
+    ws.E0, ws.H0 = w.E0, w.H0
+    return ws
+
+
+def _rel(x, ref):
+    return max(np.linalg.norm(x[:, c] - ref[:, c]) / np.linalg.norm(ref[:, c]) for c in range(ref.shape[1]))
+
+
+def _proj_rel(p, ref):
+    return max(np.sqrt(((p[c] - ref[c]) ** 2).mean() / (ref[c] ** 2).mean()) for c in range(ref.shape[0]))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "w22"])
+@pytest.mark.parametrize("tag", ["a3"])
+def test_pulse_1M_end_to_end_vs_oracle(pulse, tag, precision):
+    path = os.path.join(GOLD, f"pulse2d_1M_{tag}.npz")
+    g = np.load(path)
+    assert int(g["N"]) == pulse.N
+    w = _workload(pulse, tag, g)
+    steps, every = int(g["steps"]), int(g["energy_every"])
+    _announce(f"pulse 1M {tag} {precision}: N={w.N} alpha={w.alpha} n_hv={w.n_hv} steps={steps}")
+    if precision == "w22":
+        s = Solver.from_workload(w, precision="f32", weights="w22")
+    else:
+        s = Solver.from_workload(w, precision=precision)
+    st = s.state(w.E0, w.H0)
+    s.autotune(st, reps=5)
+    st = s.state(w.E0, w.H0)
+    r = s.run(st, steps, energy_every=every, use_graph=True)
+    E, H = s.E_original(st), s.H_original(st)
+    nodes = g["nodes"]
+    eE, eH = _rel(E[nodes], g["E"]), _rel(H[nodes], g["H"])
+    u = r["energy"]
+    eU = float(np.abs(u / g["energy"] - 1.0).max())
+    gv = np.random.default_rng(int(g["proj_seed"])).standard_normal((g["projE"].shape[1], w.N))
+    pE = np.stack([gv @ E[:, 0]])
+    pH = np.stack([gv @ H[:, c] for c in range(2)])
+    gE, gH = _proj_rel(pE, g["projE"]), _proj_rel(pH, g["projH"])
+    _announce(f"  variant {s.variant()}: sampled nodes ({nodes.size}) E {eE:.2e} H {eH:.2e}; energy {eU:.2e}; "
+              f"projections E {gE:.2e} H {gH:.2e}")
+    tol = 1e-9 if precision == "f64" else 1e-5
+    assert eE < tol and eH < tol
+    assert eU < tol
+    assert gE < tol and gH < tol
+
+
+def _inject(s, oh, oe):
+    s.set_weights(_abi.OP_CURL_H, oh["curl_w"][s.perm_h])
+    s.set_weights(_abi.OP_HV_H, oh["hv_w"][s.perm_h])
+    s.set_weights(_abi.OP_CURL_E, oe["curl_w"][s.perm])
+    s.set_weights(_abi.OP_HV_E, oe["hv_w"][s.perm])
+
+
+def test_two_sets_cavity_size_one_period_f64():
+    w = configs.tm_cavity_2d(mode="STAG2")
+    assert w.N == 51 * 51 and w.xyz_h.shape[0] == 50 * 50 and w.steps == 1000
+    _announce(f"two sets at the cavity's size: N_E={w.N} N_H={w.xyz_h.shape[0]} steps={w.steps}")
+    oh, oe = osetup.operators(w)
+    Eo, Ho, eno, _ = osetup.run_workload(w, oh, oe, energy_every=100)
+    s = Solver.from_workload(w, precision="f64")
+    st = s.state(w.E0, w.H0)
+    r = s.run(st, w.steps, energy_every=100, use_graph=True)
+    e2e = (ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho),
+           float(np.abs(r["energy"] / eno - 1).max()))
+    _inject(s, oh, oe)
+    st = s.state(w.E0, w.H0)
+    r = s.run(st, w.steps, energy_every=100, use_graph=True)
+    inj = (ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho),
+           float(np.abs(r["energy"] / eno - 1).max()))
+    _announce(f"  end to end E {e2e[0]:.2e} H {e2e[1]:.2e} energy {e2e[2]:.2e}; injected E {inj[0]:.2e} "
+              f"H {inj[1]:.2e} energy {inj[2]:.2e}")
+    assert max(e2e) < 1e-9
+    assert max(inj) < 1e-12
