@@ -63,7 +63,7 @@ def _proj_rel(p, ref):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32", "w22"])
-@pytest.mark.parametrize("tag", ["a3"])
+@pytest.mark.parametrize("tag", ["a3", "a2"])
 def test_pulse_1M_end_to_end_vs_oracle(pulse, tag, precision):
     path = os.path.join(GOLD, f"pulse2d_1M_{tag}.npz")
     g = np.load(path)
