@@ -140,8 +140,11 @@ def cpu_baseline(w, seconds=15.0):
     info = host_info()
     procs = max(1, min(16, info["usable_cores"] or 1))
     t0 = time.time()
+    log(f"cpu oracle: set-up on {procs} worker processes")
     st = knn.knn_cells(w.xyz, max(w.n, w.n_hv))
+    log(f"cpu oracle: stencils in {time.time() - t0:.0f} s")
     cw, hw = osetup.weights_parallel(w.xyz, st, w.n, w.m, w.n_hv, w.alpha, procs)
+    log(f"cpu oracle: weights, set-up {time.time() - t0:.0f} s")
     op = cstep.Operator({"curl_idx": st[:, :w.n], "curl_w": cw, "hv_idx": st[:, :w.n_hv], "hv_w": hw})
     del st, cw, hw
     t_setup = time.time() - t0
@@ -205,6 +208,7 @@ def kernels_only(args):
     the same autotuned variant the benchmark uses, from rbffd_half launches
     alone (no graph replay): the process runs only the set-up, the tuner and
     these launches, for per-kernel profiler counters."""
+    import numpy as np
     import torch
     from synth import configs
     from paper_2508_18205_amd import Solver
@@ -232,6 +236,29 @@ def kernels_only(args):
                          "GBs": round(2 * ca.numel() * 4 / (us * 1e-6) / 1e9, 1)}
             log(f"copy: {out[name]}")
             del ca, cb
+            torch.cuda.empty_cache()
+            continue
+        if name == "batch64":
+            # the K = 64 batch on the 250k-node set: whole steps (H and E
+            # updates), launched one by one
+            wb = configs.batched_2d(scale=args.scale, K=64)
+            sb = Solver.from_workload(wb, precision="f32", K=64)
+            stb = sb.state_batched(wb.E0_batch, np.zeros((64, wb.N, 2)))
+            if not args.no_tune:
+                sb.autotune(stb, reps=3)
+                stb = sb.state_batched(wb.E0_batch, np.zeros((64, wb.N, 2)))
+            sb.step(stb, 1)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sb.step(stb, args.kernel_reps)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
+            out[name] = {"N": wb.N, "K": 64, "step_us": round(us, 2),
+                         "field_node_steps_per_s": wb.N * 64 / (us * 1e-6), "variant": sb.variant()}
+            log(f"{name}: {out[name]}")
+            del sb, stb
             torch.cuda.empty_cache()
             continue
         wl, _, prec = name.partition("_")
@@ -268,8 +295,8 @@ def main():
     ap.add_argument("--kernels", default=None,
                     help="profiling mode: only time the half-step kernels, launched one by one (no graph replay), "
                          "for a comma-separated list of pulse2d_f32, pulse2d_f64, pulse2d_w22, cube3d_f32, "
-                         "cube3d_f64 (and copy: the 2 GiB streaming copy probe); prints one JSON line of average "
-                         "launch times")
+                         "cube3d_f64 (and copy: the 2 GiB streaming copy probe; batch64: whole steps of the K = 64 "
+                         "batch); prints one JSON line of average launch times")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library has no multi-GPU path "
