@@ -6,8 +6,12 @@
 // neighbour gather is one contiguous 256-byte row.  The grid is persistent:
 // a fixed number of resident workgroups strides over (node, field-chunk)
 // items, so the same wavefront keeps streaming through neighbouring nodes.
-// The update is the same eq. 19 step as the single-field kernels
-// (Kolar-Pozun & Kosec, arXiv 2508.18205, Section 5), in difference form.
+// The update is the eq. 19 step of the single-field kernels (Kolar-Pozun &
+// Kosec, arXiv 2508.18205, Section 5) with every operator summed as eq. 16
+// writes it, over the whole stencil with the centre's own weight, rather than
+// in the single-field kernels' difference form: a batch is bound by its
+// arithmetic, not by memory, and this form needs one FMA per weight and
+// field where the difference form needs a subtraction as well.
 #include <algorithm>
 #include "common.h"
 
@@ -20,6 +24,7 @@ struct BA {
     const int32_t* idx;   // [N][S]
     const float* wc;      // [N][2][C]
     const float* wh;      // [N][V]
+    const float* w0;      // [N][4] centre weights (curl x, curl y, hyperviscosity)
     int64_t N;
     int K, KC;            // fields, 64-field chunks
     int S, C, V;          // padded slot counts (multiples of 4)
@@ -45,7 +50,8 @@ __global__ __launch_bounds__(256) void k_hb(BA a) {
         const float e0 = a.E[i * K + kk];
         const float hx0 = a.H[(i * 2 + 0) * K + kk], hy0 = a.H[(i * 2 + 1) * K + kk];
         const float G = a.gk[kk];
-        float dx = 0.f, dy = 0.f, vx = 0.f, vy = 0.f;
+        const float* c0 = a.w0 + i * 4;
+        float dx = c0[0] * e0, dy = c0[1] * e0, vx = c0[2] * hx0, vy = c0[2] * hy0;
         const int32_t* pi = a.idx + i * a.S;
         const float* px = a.wc + (i * 2 + 0) * a.C;
         const float* py = a.wc + (i * 2 + 1) * a.C;
@@ -54,22 +60,22 @@ __global__ __launch_bounds__(256) void k_hb(BA a) {
         int s = 0;
         for (; s < both; ++s) {
             const int64_t j = pi[s];
-            const float de = a.E[j * K + kk] - e0;
-            dx += px[s] * de;
-            dy += py[s] * de;
-            vx += ph[s] * (a.H[(j * 2 + 0) * K + kk] - hx0);
-            vy += ph[s] * (a.H[(j * 2 + 1) * K + kk] - hy0);
+            const float e = a.E[j * K + kk];
+            dx += px[s] * e;
+            dy += py[s] * e;
+            vx += ph[s] * a.H[(j * 2 + 0) * K + kk];
+            vy += ph[s] * a.H[(j * 2 + 1) * K + kk];
         }
         for (; s < a.C; ++s) {
             const int64_t j = pi[s];
-            const float de = a.E[j * K + kk] - e0;
-            dx += px[s] * de;
-            dy += py[s] * de;
+            const float e = a.E[j * K + kk];
+            dx += px[s] * e;
+            dy += py[s] * e;
         }
         for (; s < a.V; ++s) {
             const int64_t j = pi[s];
-            vx += ph[s] * (a.H[(j * 2 + 0) * K + kk] - hx0);
-            vy += ph[s] * (a.H[(j * 2 + 1) * K + kk] - hy0);
+            vx += ph[s] * a.H[(j * 2 + 0) * K + kk];
+            vy += ph[s] * a.H[(j * 2 + 1) * K + kk];
         }
         if (on) {
             a.out[(i * 2 + 0) * K + k] = hx0 + a.a * (-dy + G * vx);
@@ -93,7 +99,10 @@ __global__ __launch_bounds__(256) void k_eb(BA a) {
         const float e0 = a.E[i * K + kk];
         const float hx0 = a.H[(i * 2 + 0) * K + kk], hy0 = a.H[(i * 2 + 1) * K + kk];
         const float G = a.gk[kk];
-        float cu = 0.f, ve = 0.f;
+        const float* c0 = a.w0 + i * 4;
+        // curl H = D^dx Hy - D^dy Hx
+        float cu = c0[0] * hy0, ve = c0[2] * e0;
+        cu -= c0[1] * hx0;
         const int32_t* pi = a.idx + i * a.S;
         const float* px = a.wc + (i * 2 + 0) * a.C;
         const float* py = a.wc + (i * 2 + 1) * a.C;
@@ -102,16 +111,18 @@ __global__ __launch_bounds__(256) void k_eb(BA a) {
         int s = 0;
         for (; s < both; ++s) {
             const int64_t j = pi[s];
-            cu += px[s] * (a.H[(j * 2 + 1) * K + kk] - hy0) - py[s] * (a.H[(j * 2 + 0) * K + kk] - hx0);
-            ve += ph[s] * (a.E[j * K + kk] - e0);
+            cu += px[s] * a.H[(j * 2 + 1) * K + kk];
+            cu -= py[s] * a.H[(j * 2 + 0) * K + kk];
+            ve += ph[s] * a.E[j * K + kk];
         }
         for (; s < a.C; ++s) {
             const int64_t j = pi[s];
-            cu += px[s] * (a.H[(j * 2 + 1) * K + kk] - hy0) - py[s] * (a.H[(j * 2 + 0) * K + kk] - hx0);
+            cu += px[s] * a.H[(j * 2 + 1) * K + kk];
+            cu -= py[s] * a.H[(j * 2 + 0) * K + kk];
         }
         for (; s < a.V; ++s) {
             const int64_t j = pi[s];
-            ve += ph[s] * (a.E[j * K + kk] - e0);
+            ve += ph[s] * a.E[j * K + kk];
         }
         if (on) a.out[i * K + k] = (a.emask[i] & 1) ? e0 + a.a * (cu + G * ve) : 0.f;
     }
@@ -135,6 +146,7 @@ struct BLA {
     const int32_t* hoff;  // [256-node tiles + 1]
     const float* wc;      // [tiles][C4][2][64][4]
     const float* wh;      // [tiles][V4][64][4]
+    const float* w0;      // [N][4] centre weights (curl x, curl y, hyperviscosity)
     int64_t N, tiles;
     int K, KS, C4, V4, Q8, xcd;
     float a;
@@ -152,12 +164,19 @@ __device__ __forceinline__ f4 ldf4(const float* p) {
 __device__ __forceinline__ void stf4(float* p, const f4& v) {
     *reinterpret_cast<float4*>(p) = make_float4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ void fma4(f4& acc, float w, const f4& a, const f4& b) {
-    acc.x += w * (a.x - b.x);
-    acc.y += w * (a.y - b.y);
-    acc.z += w * (a.z - b.z);
-    acc.w += w * (a.w - b.w);
+__device__ __forceinline__ void fma4(f4& acc, float w, const f4& a) {
+    acc.x += w * a.x;
+    acc.y += w * a.y;
+    acc.z += w * a.z;
+    acc.w += w * a.w;
 }
+__device__ __forceinline__ void fms4(f4& acc, float w, const f4& a) {
+    acc.x -= w * a.x;
+    acc.y -= w * a.y;
+    acc.z -= w * a.z;
+    acc.w -= w * a.w;
+}
+__device__ __forceinline__ f4 mul4(float w, const f4& a) { return {w * a.x, w * a.y, w * a.z, w * a.w}; }
 __device__ __forceinline__ int posq(const uint4& v, int half, int u) {
     const uint32_t w = half ? (u < 2 ? v.z : v.w) : (u < 2 ? v.x : v.y);
     return (int)((u & 1) ? (w >> 16) : (w & 0xFFFFu));
@@ -248,22 +267,21 @@ __device__ __forceinline__ void h_read(const BLA& a, const float* sm, uint4 lp, 
     }
 }
 
-__device__ __forceinline__ void h_sum(const BLA& a, int q, const HChunk& c, const f4& e0, const f4& hx0, const f4& hy0,
-                                      f4& dx, f4& dy, f4& vx, f4& vy) {
+__device__ __forceinline__ void h_sum(const BLA& a, int q, const HChunk& c, f4& dx, f4& dy, f4& vx, f4& vy) {
     if (q < a.C4) {
         const float wxs[4] = {c.wx.x, c.wx.y, c.wx.z, c.wx.w}, wys[4] = {c.wy.x, c.wy.y, c.wy.z, c.wy.w};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            fma4(dx, wxs[u], c.e[u], e0);
-            fma4(dy, wys[u], c.e[u], e0);
+            fma4(dx, wxs[u], c.e[u]);
+            fma4(dy, wys[u], c.e[u]);
         }
     }
     if (q < a.V4) {
         const float whs[4] = {c.wh.x, c.wh.y, c.wh.z, c.wh.w};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            fma4(vx, whs[u], c.x[u], hx0);
-            fma4(vy, whs[u], c.y[u], hy0);
+            fma4(vx, whs[u], c.x[u]);
+            fma4(vy, whs[u], c.y[u]);
         }
     }
 }
@@ -285,31 +303,74 @@ __device__ __forceinline__ void e_read(const BLA& a, const float* sm, uint4 lp, 
     }
 }
 
-__device__ __forceinline__ void e_sum(const BLA& a, int q, const EChunk& c, const f4& e0, const f4& hx0, const f4& hy0,
-                                      f4& cu, f4& ve) {
+__device__ __forceinline__ void e_sum(const BLA& a, int q, const EChunk& c, f4& cu, f4& ve) {
     if (q < a.C4) {
         const float wxs[4] = {c.wx.x, c.wx.y, c.wx.z, c.wx.w}, wys[4] = {c.wy.x, c.wy.y, c.wy.z, c.wy.w};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            // curl H = D^dx Hy - D^dy Hx, in the single-field kernels' order
-            const f4& hx = c.hx[u];
-            const f4& hy = c.hy[u];
-            cu.x += wxs[u] * (hy.x - hy0.x) - wys[u] * (hx.x - hx0.x);
-            cu.y += wxs[u] * (hy.y - hy0.y) - wys[u] * (hx.y - hx0.y);
-            cu.z += wxs[u] * (hy.z - hy0.z) - wys[u] * (hx.z - hx0.z);
-            cu.w += wxs[u] * (hy.w - hy0.w) - wys[u] * (hx.w - hx0.w);
+            // curl H = D^dx Hy - D^dy Hx
+            fma4(cu, wxs[u], c.hy[u]);
+            fms4(cu, wys[u], c.hx[u]);
         }
     }
     if (q < a.V4) {
         const float whs[4] = {c.wh.x, c.wh.y, c.wh.z, c.wh.w};
 #pragma unroll
-        for (int u = 0; u < 4; ++u) fma4(ve, whs[u], c.e[u], e0);
+        for (int u = 0; u < 4; ++u) fma4(ve, whs[u], c.e[u]);
     }
 }
 
-// positions of chunk pair m (chunks 2m, 2m + 1), zero past the last pair
-__device__ __forceinline__ uint4 pair_pos(const uint4* pl, int m, int npairs) {
-    return m < npairs ? pl[m * RBFFD_TILE] : make_uint4(0, 0, 0, 0);
+// A chunk with both curl and hyperviscosity slots: its twelve LDS reads are
+// issued together, then summed (no per-part branches, so that the reads of
+// one chunk are all in flight before the first sum waits).
+template <int KSL, int HF>
+__device__ __forceinline__ void h_read_full(const float* sm, uint4 lp, int fq, HChunk& c) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int k = posq(lp, HF, u);
+        c.e[u] = ldf4(row<KSL>(sm, k, 0, fq));
+        c.x[u] = ldf4(row<KSL>(sm, k, 1, fq));
+        c.y[u] = ldf4(row<KSL>(sm, k, 2, fq));
+    }
+}
+
+__device__ __forceinline__ void h_sum_full(const HChunk& c, const f4& wx, const f4& wy, const f4& wh, f4& dx, f4& dy,
+                                           f4& vx, f4& vy) {
+    const float wxs[4] = {wx.x, wx.y, wx.z, wx.w}, wys[4] = {wy.x, wy.y, wy.z, wy.w};
+    const float whs[4] = {wh.x, wh.y, wh.z, wh.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        fma4(dx, wxs[u], c.e[u]);
+        fma4(dy, wys[u], c.e[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        fma4(vx, whs[u], c.x[u]);
+        fma4(vy, whs[u], c.y[u]);
+    }
+}
+
+template <int KSL, int HF>
+__device__ __forceinline__ void e_read_full(const float* sm, uint4 lp, int fq, EChunk& c) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int k = posq(lp, HF, u);
+        c.hx[u] = ldf4(row<KSL>(sm, k, 1, fq));
+        c.hy[u] = ldf4(row<KSL>(sm, k, 2, fq));
+        c.e[u] = ldf4(row<KSL>(sm, k, 0, fq));
+    }
+}
+
+__device__ __forceinline__ void e_sum_full(const EChunk& c, const f4& wx, const f4& wy, const f4& wh, f4& cu, f4& ve) {
+    const float wxs[4] = {wx.x, wx.y, wx.z, wx.w}, wys[4] = {wy.x, wy.y, wy.z, wy.w};
+    const float whs[4] = {wh.x, wh.y, wh.z, wh.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        fma4(cu, wxs[u], c.hy[u]);
+        fms4(cu, wys[u], c.hx[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) fma4(ve, whs[u], c.e[u]);
 }
 
 template <int TPN>
@@ -329,29 +390,50 @@ __global__ __launch_bounds__(RBFFD_WGT_BATCH * TPN) void k_hbl(BLA a) {
     const int64_t K = a.K;
     const int k0 = ks * KSL + fq * 4;
     const f4 e0 = ldf4(a.E + i * K + k0), hx0 = ldf4(a.H + (i * 2) * K + k0), hy0 = ldf4(a.H + (i * 2 + 1) * K + k0);
-    f4 dx{0, 0, 0, 0}, dy{0, 0, 0, 0}, vx{0, 0, 0, 0}, vy{0, 0, 0, 0};
+    // the centre's own terms of eq. 16 first
+    const f4 c0 = ldf4(a.w0 + i * 4);
+    f4 dx = mul4(c0.x, e0), dy = mul4(c0.y, e0), vx = mul4(c0.z, hx0), vy = mul4(c0.z, hy0);
     const uint4* pl = a.lidx + t64 * a.Q8 * RBFFD_TILE + ln;
     const float* pc = a.wc + (t64 * a.C4 * 2 * RBFFD_TILE + ln) * 4;
     const float* ph = a.wh + (t64 * a.V4 * RBFFD_TILE + ln) * 4;
-    const int qm = max(a.C4, a.V4);
+    const int qm = max(a.C4, a.V4), qb = min(a.C4, a.V4);
     const int np = (qm + 1) >> 1;
-    // the weights and halo positions of chunk q + 1 are loaded while chunk q
-    // is read from LDS and summed
-    uint4 lp = pair_pos(pl, 0, np), lpn = pair_pos(pl, 1, np);
     HChunk A;
-    f4 nx{0, 0, 0, 0}, ny{0, 0, 0, 0}, nh{0, 0, 0, 0};
-    w_read(a, 0, pc, ph, nx, ny, nh);
-    for (int q = 0; q < qm; ++q) {
-        A.wx = nx;
-        A.wy = ny;
-        A.wh = nh;
-        if (q > 0 && (q & 1) == 0) {            // chunks 2m, 2m + 1 use pair m
+    // chunk pairs in which every chunk has both parts: the weights of the
+    // next chunk and the positions of the next pair are loaded while the
+    // current chunk is read from LDS and summed (indices clamped to the last
+    // chunk and pair, so the loads need no branch)
+    int q = 0;
+    {
+        f4 wx0 = ldf4(pc), wy0 = ldf4(pc + RBFFD_TILE * 4), wh0 = ldf4(ph);
+        uint4 lp = pl[0];
+        for (; q + 2 <= qb; q += 2) {
+            const uint4 lpn = pl[min((q >> 1) + 1, np - 1) * RBFFD_TILE];
+            const f4 wx1 = ldf4(pc + ((q + 1) * 2 + 0) * RBFFD_TILE * 4);
+            const f4 wy1 = ldf4(pc + ((q + 1) * 2 + 1) * RBFFD_TILE * 4);
+            const f4 wh1 = ldf4(ph + (q + 1) * RBFFD_TILE * 4);
+            h_read_full<KSL, 0>(sm, lp, fq, A);
+            h_sum_full(A, wx0, wy0, wh0, dx, dy, vx, vy);
+            const int qc = min(q + 2, a.C4 - 1), qv = min(q + 2, a.V4 - 1);
+            wx0 = ldf4(pc + (qc * 2 + 0) * RBFFD_TILE * 4);
+            wy0 = ldf4(pc + (qc * 2 + 1) * RBFFD_TILE * 4);
+            wh0 = ldf4(ph + qv * RBFFD_TILE * 4);
+            h_read_full<KSL, 1>(sm, lp, fq, A);
+            h_sum_full(A, wx1, wy1, wh1, dx, dy, vx, vy);
             lp = lpn;
-            lpn = pair_pos(pl, (q >> 1) + 1, np);
         }
-        if (q + 1 < qm) w_read(a, q + 1, pc, ph, nx, ny, nh);
+    }
+    // the rest: an odd last chunk with both parts, then the chunks past the
+    // shorter part
+    for (; q < qm; ++q) {
+        f4 zx{0, 0, 0, 0}, zy{0, 0, 0, 0}, zh{0, 0, 0, 0};
+        w_read(a, q, pc, ph, zx, zy, zh);
+        A.wx = zx;
+        A.wy = zy;
+        A.wh = zh;
+        const uint4 lp = pl[(q >> 1) * RBFFD_TILE];
         h_read<KSL>(a, sm, lp, q, fq, A);
-        h_sum(a, q, A, e0, hx0, hy0, dx, dy, vx, vy);
+        h_sum(a, q, A, dx, dy, vx, vy);
     }
     const float Af = a.a;
     const f4 G = ldf4(a.gk + k0);
@@ -378,27 +460,44 @@ __global__ __launch_bounds__(RBFFD_WGT_BATCH * TPN) void k_ebl(BLA a) {
     const int64_t K = a.K;
     const int k0 = ks * KSL + fq * 4;
     const f4 e0 = ldf4(a.E + i * K + k0), hx0 = ldf4(a.H + (i * 2) * K + k0), hy0 = ldf4(a.H + (i * 2 + 1) * K + k0);
-    f4 cu{0, 0, 0, 0}, ve{0, 0, 0, 0};
+    const f4 c0 = ldf4(a.w0 + i * 4);
+    f4 cu = mul4(c0.x, hy0), ve = mul4(c0.z, e0);
+    fms4(cu, c0.y, hx0);
     const uint4* pl = a.lidx + t64 * a.Q8 * RBFFD_TILE + ln;
     const float* pc = a.wc + (t64 * a.C4 * 2 * RBFFD_TILE + ln) * 4;
     const float* ph = a.wh + (t64 * a.V4 * RBFFD_TILE + ln) * 4;
-    const int qm = max(a.C4, a.V4);
+    const int qm = max(a.C4, a.V4), qb = min(a.C4, a.V4);
     const int np = (qm + 1) >> 1;
-    uint4 lp = pair_pos(pl, 0, np), lpn = pair_pos(pl, 1, np);
     EChunk A;
-    f4 nx{0, 0, 0, 0}, ny{0, 0, 0, 0}, nh{0, 0, 0, 0};
-    w_read(a, 0, pc, ph, nx, ny, nh);
-    for (int q = 0; q < qm; ++q) {
-        A.wx = nx;
-        A.wy = ny;
-        A.wh = nh;
-        if (q > 0 && (q & 1) == 0) {            // chunks 2m, 2m + 1 use pair m
+    int q = 0;
+    {
+        f4 wx0 = ldf4(pc), wy0 = ldf4(pc + RBFFD_TILE * 4), wh0 = ldf4(ph);
+        uint4 lp = pl[0];
+        for (; q + 2 <= qb; q += 2) {
+            const uint4 lpn = pl[min((q >> 1) + 1, np - 1) * RBFFD_TILE];
+            const f4 wx1 = ldf4(pc + ((q + 1) * 2 + 0) * RBFFD_TILE * 4);
+            const f4 wy1 = ldf4(pc + ((q + 1) * 2 + 1) * RBFFD_TILE * 4);
+            const f4 wh1 = ldf4(ph + (q + 1) * RBFFD_TILE * 4);
+            e_read_full<KSL, 0>(sm, lp, fq, A);
+            e_sum_full(A, wx0, wy0, wh0, cu, ve);
+            const int qc = min(q + 2, a.C4 - 1), qv = min(q + 2, a.V4 - 1);
+            wx0 = ldf4(pc + (qc * 2 + 0) * RBFFD_TILE * 4);
+            wy0 = ldf4(pc + (qc * 2 + 1) * RBFFD_TILE * 4);
+            wh0 = ldf4(ph + qv * RBFFD_TILE * 4);
+            e_read_full<KSL, 1>(sm, lp, fq, A);
+            e_sum_full(A, wx1, wy1, wh1, cu, ve);
             lp = lpn;
-            lpn = pair_pos(pl, (q >> 1) + 1, np);
         }
-        if (q + 1 < qm) w_read(a, q + 1, pc, ph, nx, ny, nh);
+    }
+    for (; q < qm; ++q) {
+        f4 zx{0, 0, 0, 0}, zy{0, 0, 0, 0}, zh{0, 0, 0, 0};
+        w_read(a, q, pc, ph, zx, zy, zh);
+        A.wx = zx;
+        A.wy = zy;
+        A.wh = zh;
+        const uint4 lp = pl[(q >> 1) * RBFFD_TILE];
         e_read<KSL>(a, sm, lp, q, fq, A);
-        e_sum(a, q, A, e0, hx0, hy0, cu, ve);
+        e_sum(a, q, A, cu, ve);
     }
     const float Af = a.a;
     const f4 G = ldf4(a.gk + k0);
@@ -414,6 +513,7 @@ BA make_args(const rbffd_plan* p) {
     a.idx = o.bidx;
     a.wc = o.bwc;
     a.wh = o.bwh;
+    a.w0 = o.bw0;
     a.N = o.Nt;
     a.K = p->K;
     a.KC = (int)cdiv(p->K, 64);
@@ -454,6 +554,7 @@ void launch_half_staged(const rbffd_plan* p, const rbffd_fields* f, int c, bool 
     a.hoff = ob.hoff;
     a.wc = (const float*)ob.pwc;
     a.wh = (const float*)ob.pwh;
+    a.w0 = ob.bw0;
     a.N = ob.Nt;
     a.tiles = ob.tiles;
     a.K = p->K;

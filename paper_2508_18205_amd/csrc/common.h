@@ -54,6 +54,7 @@ struct OpBlock {
     int32_t* bidx = nullptr;       // [Nt][S4*4]
     float* bwc = nullptr;          // [Nt][dim][C4*4]
     float* bwh = nullptr;          // [Nt][V4*4]
+    float* bw0 = nullptr;          // [Nt][4]: centre weights (curl x, curl y, hyperviscosity, 0)
     // LDS staging (collocated): per 256-node workgroup tile, the sorted unique
     // source nodes of all its stencils ("halo list") and, per node and slot,
     // the 16-bit position of the slot's node in that list

@@ -114,6 +114,7 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int cb, int K, bool adjo
         o.bidx = b.take<int32_t>(o.Nt * o.S4 * 4);
         o.bwc = b.take<float>(o.Nt * dim * o.C4 * 4);
         o.bwh = b.take<float>(o.Nt * o.V4 * 4);
+        o.bw0 = b.take<float>(o.Nt * 4);
     }
     if (adjoint) {
         o.t_off = b.take<int64_t>(o.tiles + 1);

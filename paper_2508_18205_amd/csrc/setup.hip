@@ -886,10 +886,17 @@ __global__ void k_pack_cross(const int32_t* stc, const int32_t* sth, const doubl
     }
 }
 
+// K-field batch (2D): the neighbour slots as in the union pack, plus the
+// centre weights of the curl and hyperviscosity operators in FP32 (the batch
+// kernels sum eq. 16 over the whole stencil, centre included)
 __global__ void k_pack_batched(const int32_t* st, const double* wc, const double* wh, int64_t N, int ns, int n, int nh,
-                               int d, int C4, int V4, int S4, int32_t* bidx, float* bwc, float* bwh) {
+                               int d, int C4, int V4, int S4, int32_t* bidx, float* bwc, float* bwh, float* bw0) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
+    bw0[i * 4 + 0] = (float)wc[(i * d + 0) * n];
+    bw0[i * 4 + 1] = d > 1 ? (float)wc[(i * d + 1) * n] : 0.0f;
+    bw0[i * 4 + 2] = nh > 0 ? (float)wh[i * nh] : 0.0f;
+    bw0[i * 4 + 3] = 0.0f;
     for (int s4 = 0; s4 < S4 * 4; ++s4) {
         const int s = 1 + s4;
         bidx[i * S4 * 4 + s4] = s < ns ? st[i * ns + s] : (int)i;
@@ -1503,7 +1510,7 @@ static int pack_block(rbffd_plan* p, const OpBlock& o, hipStream_t st) {
                                (float*)o.pwh);
         if (p->K > 1)
             hipLaunchKernelGGL(k_pack_batched, dim3(blocks(o.Nt)), dim3(256), 0, st, o.st_union, o.wc, o.wh, o.Nt, o.ns,
-                               o.n, o.nh, d, o.C4, o.V4, o.S4, o.bidx, o.bwc, o.bwh);
+                               o.n, o.nh, d, o.C4, o.V4, o.S4, o.bidx, o.bwc, o.bwh, o.bw0);
     } else {
         if (f64)
             hipLaunchKernelGGL(k_pack_cross<double>, dim3(blocks(G)), dim3(256), 0, st, o.st_curl, o.st_hv, o.wc, o.wh,
