@@ -364,10 +364,14 @@ int rbffd_autotune(rbffd_plan* plan, rbffd_fields* f, int32_t reps, void* stream
  * lds << 17 | persist << 20 (block = threads per workgroup of the unstaged
  * kernels, xcd = XCD-aware workgroup order, lds = 0 global gathers, 1 LDS-staged
  * kernels when the plan has halo lists, 2 the same but in 3D one staged operand
- * at a time even where both fit, 3 in 2D (single field, collocated) global
+ * at a time even where both fit, and for the K-field batch persistent staged
+ * kernels whose staging wavefronts fill a second LDS buffer while the others
+ * sum, 3 in 2D (single field, collocated) global
  * gathers with four wavefronts per 64-node tile, each summing a quarter of the
  * stencil (for node sets too small to fill the chip), persist = resident
- * workgroups per CU of the K-field batch).  rbffd_set_variant sets it (block a
+ * workgroups per CU of the K-field batch's global kernels and the field-slice
+ * width of its staged ones: 16 fields for persist >= 16, 4 below 8, else 8,
+ * each where K and the LDS allow).  rbffd_set_variant sets it (block a
  * multiple of 64, <= 512, lds 0..3). */
 int rbffd_get_variant(const rbffd_plan* plan, int32_t* out_variant);
 int rbffd_set_variant(rbffd_plan* plan, int32_t block, int32_t xcd, int32_t lds, int32_t persist);

@@ -149,6 +149,8 @@ struct BLA {
     const float* w0;      // [N][4] centre weights (curl x, curl y, hyperviscosity)
     int64_t N, tiles;
     int K, KS, C4, V4, Q8, xcd;
+    int64_t items;        // (tile, slice) items
+    int64_t slice;        // floats per LDS halo-slice buffer (persistent kernels)
     float a;
     const float* gk;      // per-field gamma [K]
     const uint8_t* emask;
@@ -186,15 +188,16 @@ __device__ __forceinline__ int posq(const uint4& v, int half, int u) {
 // is piece q = it % Q of row (k, c) = divmod(it / Q, 3), and the LDS layout
 // [k][c][KSL] puts it at it * 4 floats.  Each round a thread takes SB items:
 // all their list values are loaded, then all their 16-byte field pieces, then
-// the LDS stores, so that the loads are in flight together.
+// the LDS stores, so that the loads are in flight together.  Threads t of nt
+// take part (the whole workgroup, or its staging wavefronts).
 template <int KSL>
-__device__ __forceinline__ void stage_slice(const BLA& a, float* sm, int64_t tile, int ks) {
+__device__ __forceinline__ void stage_slice(const BLA& a, float* sm, int64_t tile, int ks, int t, int nt) {
     constexpr int SB = KSL == 4 ? 4 : 8;
     constexpr int Q = KSL / 4;            // 16-byte pieces per row slice (1, 2 or 4)
     constexpr int LQ = Q == 4 ? 2 : (Q == 2 ? 1 : 0);
     const int h0 = a.hoff[tile], hc = a.hoff[tile + 1] - h0;
     const int K = a.K;
-    const int items = hc * 3 * Q, nt = (int)blockDim.x, t = (int)threadIdx.x;
+    const int items = hc * 3 * Q;
     const float* E = a.E + ks * KSL;
     const float* H = a.H + ks * KSL;
     for (int base = 0; base < items; base += SB * nt) {
@@ -373,16 +376,12 @@ __device__ __forceinline__ void e_sum_full(const EChunk& c, const f4& wx, const 
     for (int u = 0; u < 4; ++u) fma4(ve, whs[u], c.e[u]);
 }
 
+// H update of one (tile, slice) item from its staged halo slice sm, by
+// thread tid of the tile's RBFFD_WGT_BATCH * TPN
 template <int TPN>
-__global__ __launch_bounds__(RBFFD_WGT_BATCH * TPN) void k_hbl(BLA a) {
+__device__ __forceinline__ void h_item(const BLA& a, const float* sm, int64_t tile, int ks, int tid) {
     constexpr int KSL = 4 * TPN;          // fields per slice, 4 per thread
-    extern __shared__ __align__(16) float sm[];
-    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int64_t tile = wg / a.KS;
-    const int ks = wg % a.KS;
-    stage_slice<KSL>(a, sm, tile, ks);
-    __syncthreads();
-    const int nl = threadIdx.x / TPN, fq = threadIdx.x % TPN;
+    const int nl = tid / TPN, fq = tid % TPN;
     const int64_t i = tile * RBFFD_WGT_BATCH + nl;
     if (i >= a.N) return;
     const int64_t t64 = i / RBFFD_TILE;
@@ -443,16 +442,11 @@ __global__ __launch_bounds__(RBFFD_WGT_BATCH * TPN) void k_hbl(BLA a) {
                                         hy0.z + Af * (dx.z + G.z * vy.z), hy0.w + Af * (dx.w + G.w * vy.w)});
 }
 
+// E update of one (tile, slice) item (as h_item)
 template <int TPN>
-__global__ __launch_bounds__(RBFFD_WGT_BATCH * TPN) void k_ebl(BLA a) {
-    constexpr int KSL = 4 * TPN;          // fields per slice, 4 per thread
-    extern __shared__ __align__(16) float sm[];
-    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int64_t tile = wg / a.KS;
-    const int ks = wg % a.KS;
-    stage_slice<KSL>(a, sm, tile, ks);
-    __syncthreads();
-    const int nl = threadIdx.x / TPN, fq = threadIdx.x % TPN;
+__device__ __forceinline__ void e_item(const BLA& a, const float* sm, int64_t tile, int ks, int tid) {
+    constexpr int KSL = 4 * TPN;
+    const int nl = tid / TPN, fq = tid % TPN;
     const int64_t i = tile * RBFFD_WGT_BATCH + nl;
     if (i >= a.N) return;
     const int64_t t64 = i / RBFFD_TILE;
@@ -507,6 +501,63 @@ __global__ __launch_bounds__(RBFFD_WGT_BATCH * TPN) void k_ebl(BLA a) {
                                   : f4{0, 0, 0, 0});
 }
 
+// one item per workgroup: the whole workgroup stages the halo slice, then sums
+template <int TPN>
+__global__ __launch_bounds__(RBFFD_WGT_BATCH * TPN) void k_hbl(BLA a) {
+    extern __shared__ __align__(16) float sm[];
+    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int64_t tile = wg / a.KS;
+    const int ks = wg % a.KS;
+    stage_slice<4 * TPN>(a, sm, tile, ks, (int)threadIdx.x, (int)blockDim.x);
+    __syncthreads();
+    h_item<TPN>(a, sm, tile, ks, (int)threadIdx.x);
+}
+
+template <int TPN>
+__global__ __launch_bounds__(RBFFD_WGT_BATCH * TPN) void k_ebl(BLA a) {
+    extern __shared__ __align__(16) float sm[];
+    const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int64_t tile = wg / a.KS;
+    const int ks = wg % a.KS;
+    stage_slice<4 * TPN>(a, sm, tile, ks, (int)threadIdx.x, (int)blockDim.x);
+    __syncthreads();
+    e_item<TPN>(a, sm, tile, ks, (int)threadIdx.x);
+}
+
+// ---- persistent batch with staging wavefronts ------------------------------
+// A resident workgroup walks the items v, v + G, v + 2G, ... (v its
+// XCD-ordered index, G the grid).  Its first RBFFD_WGT_BATCH * TPN threads
+// sum item n from one LDS buffer while the last 64 * TPN threads (the
+// staging wavefronts) copy the halo slice of item n + 1 into the other, so
+// that the halo loads are in flight while the sums run; one barrier per item
+// hands the buffers over.  Every thread makes the same number of trips
+// through the loop, so every barrier is reached by the whole workgroup.
+template <int TPN, bool HUPD>
+__global__ __launch_bounds__(RBFFD_WGT_BATCH * TPN + 64 * TPN) void k_bpers(BLA a) {
+    constexpr int NC = RBFFD_WGT_BATCH * TPN, NP = 64 * TPN;
+    extern __shared__ __align__(16) float sm[];
+    const int64_t n = a.items, G = gridDim.x;
+    const int64_t v = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int t = (int)threadIdx.x;
+    const bool prod = t >= NC;
+    int b = 0;
+    if (prod && v < n) stage_slice<4 * TPN>(a, sm, v / a.KS, (int)(v % a.KS), t - NC, NP);
+    __syncthreads();
+    for (int64_t it = v; it < n; it += G) {
+        float* cur = sm + (int64_t)b * a.slice;
+        if (prod) {
+            const int64_t nx = it + G;
+            if (nx < n) stage_slice<4 * TPN>(a, sm + (int64_t)(b ^ 1) * a.slice, nx / a.KS, (int)(nx % a.KS), t - NC, NP);
+        } else if (HUPD) {
+            h_item<TPN>(a, cur, it / a.KS, (int)(it % a.KS), t);
+        } else {
+            e_item<TPN>(a, cur, it / a.KS, (int)(it % a.KS), t);
+        }
+        __syncthreads();
+        b ^= 1;
+    }
+}
+
 BA make_args(const rbffd_plan* p) {
     const OpBlock& o = p->opH;
     BA a{};
@@ -528,14 +579,17 @@ BA make_args(const rbffd_plan* p) {
 // slice width: 16 fields (4 threads per node) when the tile's halo slice fits
 // the LDS budget and the variant asks for it (persist >= 16), 4 fields (one
 // thread per node, the smallest LDS footprint: more resident workgroups) for
-// persist < 8, else 8 (2 threads per node)
+// persist < 8, else 8 (2 threads per node).  The persistent kernels (lds = 2)
+// hold two slices per workgroup.
 int slice_tpn(const rbffd_plan* p) {
     if (!p->var.lds || p->opH.hmax <= 0) return 0;
-    const int64_t per16 = (int64_t)3 * 16 * 4;
-    if (p->var.persist >= 16 && p->K % 16 == 0 && p->opH.hmax * per16 <= RBFFD_LDS_BUDGET_BATCH) return 4;
-    if (p->var.persist < 8 && p->K % 4 == 0) return 1;
-    if (p->K % 8 == 0) return 2;
-    if (p->K % 4 == 0) return 1;
+    const bool pers = p->var.lds == 2;
+    const int64_t cap = pers ? RBFFD_LDS_CU : RBFFD_LDS_BUDGET_BATCH;
+    auto fits = [&](int ksl) { return (pers ? 2 : 1) * p->opH.hmax * 3 * ksl * 4 <= cap; };
+    if (p->var.persist >= 16 && p->K % 16 == 0 && fits(16)) return 4;
+    if (p->var.persist < 8 && p->K % 4 == 0 && fits(4)) return 1;
+    if (p->K % 8 == 0 && fits(8)) return 2;
+    if (p->K % 4 == 0 && fits(4)) return 1;
     return 0;
 }
 
@@ -565,20 +619,46 @@ void launch_half_staged(const rbffd_plan* p, const rbffd_fields* f, int c, bool 
     a.xcd = p->var.xcd;
     a.gk = p->gk;
     a.emask = p->E.emask;
-    const dim3 grid((unsigned)(ob.nwg * a.KS)), block(RBFFD_WGT_BATCH * tpn);
-    const size_t lds = (size_t)ob.hmax * 3 * ksl * sizeof(float);
+    a.items = ob.nwg * a.KS;
+    a.slice = (int64_t)ob.hmax * 3 * ksl;
     a.E = (const float*)f->E[c];
     if (hupd) {
         a.H = (const float*)f->H[c];
         a.out = (float*)f->H[o];
         a.a = (float)(p->dt / p->p.mu0);
-        if (tpn == 4) hipLaunchKernelGGL(k_hbl<4>, grid, block, lds, st, a);
-        else if (tpn == 2) hipLaunchKernelGGL(k_hbl<2>, grid, block, lds, st, a);
-        else hipLaunchKernelGGL(k_hbl<1>, grid, block, lds, st, a);
     } else {
         a.H = (const float*)f->H[o];
         a.out = (float*)f->E[o];
         a.a = (float)(p->dt / p->p.eps0);
+    }
+    if (p->var.lds == 2) {
+        // persistent: as many resident workgroups as the CUs' LDS and
+        // thread slots hold, never more than there are items
+        const size_t lds = 2 * (size_t)a.slice * sizeof(float);
+        const int threads = (RBFFD_WGT_BATCH + 64) * tpn;
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(RBFFD_LDS_CU / (int64_t)lds, 2048 / threads));
+        const dim3 grid((unsigned)std::min<int64_t>(a.items, cus * per_cu)), block(threads);
+        if (tpn == 4) {
+            if (hupd) hipLaunchKernelGGL((k_bpers<4, true>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_bpers<4, false>), grid, block, lds, st, a);
+        } else if (tpn == 2) {
+            if (hupd) hipLaunchKernelGGL((k_bpers<2, true>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_bpers<2, false>), grid, block, lds, st, a);
+        } else {
+            if (hupd) hipLaunchKernelGGL((k_bpers<1, true>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_bpers<1, false>), grid, block, lds, st, a);
+        }
+        return;
+    }
+    const dim3 grid((unsigned)a.items), block(RBFFD_WGT_BATCH * tpn);
+    const size_t lds = (size_t)a.slice * sizeof(float);
+    if (hupd) {
+        if (tpn == 4) hipLaunchKernelGGL(k_hbl<4>, grid, block, lds, st, a);
+        else if (tpn == 2) hipLaunchKernelGGL(k_hbl<2>, grid, block, lds, st, a);
+        else hipLaunchKernelGGL(k_hbl<1>, grid, block, lds, st, a);
+    } else {
         if (tpn == 4) hipLaunchKernelGGL(k_ebl<4>, grid, block, lds, st, a);
         else if (tpn == 2) hipLaunchKernelGGL(k_ebl<2>, grid, block, lds, st, a);
         else hipLaunchKernelGGL(k_ebl<1>, grid, block, lds, st, a);

@@ -20,6 +20,7 @@
                                   // resident workgroups; the tuner also tries one at a time)
 #define RBFFD_KSLICE 16           // widest field slice of the staged K-field batch
 #define RBFFD_LDS_BUDGET_BATCH 122880
+#define RBFFD_LDS_CU 163840       // LDS of one CU (gfx950)
 
 // ---------------------------------------------------------------------------
 // Device-side layout of one operator block (the weights applied in one half

@@ -1793,8 +1793,10 @@ extern "C" int rbffd_autotune(rbffd_plan* p, rbffd_fields* f, int32_t reps, void
     }
     if (staged) {
         if (p->K > 1) {
-            // staged batch: 4-field (persist < 8), 8-field or 16-field slices
-            for (int pe : {4, 8, 16}) cand.push_back(Variant{256, 1, pe, 1});
+            // staged batch: 4-field (persist < 8), 8-field or 16-field slices,
+            // one item per workgroup or persistent with staging wavefronts
+            for (int l : {1, 2})
+                for (int pe : {4, 8, 16}) cand.push_back(Variant{256, 1, pe, l});
         } else {
             for (int x : {0, 1}) cand.push_back(Variant{256, x, 8, 1});
             // 3D with both operands fitting: also the one-operand-at-a-time kernels

@@ -245,9 +245,10 @@ def test_run_energy_sources_receivers_graph():
     assert np.abs(T - tr).max() <= 1e-12 * np.abs(tr).max()
 
 
-@pytest.mark.parametrize("lds,persist", [(1, 16), (1, 8), (1, 4), (0, 8)])
+@pytest.mark.parametrize("lds,persist", [(1, 16), (1, 8), (1, 4), (2, 16), (2, 4), (0, 8)])
 def test_batched_equals_single_runs(lds, persist):
-    # staged kernels with 16-, 8- and 4-field slices, and the global kernel
+    # staged kernels with 16-, 8- and 4-field slices (one item per workgroup,
+    # and persistent), and the global kernel
     _announce(f"K-field batch vs single runs (staged={lds}, persist={persist})")
     w = configs.batched_2d(n_side=60, K=64, steps=100, chat=1e-3)
     sb = Solver.from_workload(w, precision="f32", K=64)
@@ -379,7 +380,7 @@ def test_batch_on_a_partial_tile():
     E0b = np.stack([fields.gaussian_pulse(xyz, (0.3 + 0.05 * k, 0.5), 0.2)[0] for k in range(8)])
     sb = Solver.from_workload(w, precision="f32", K=8)
     s1 = Solver.from_workload(w, precision="f32")
-    for lds, pe in ((1, 8), (1, 4), (0, 8)):
+    for lds, pe in ((1, 8), (1, 4), (2, 8), (0, 8)):
         sb.set_variant(block=256, xcd=1, lds=lds, persist=pe)
         stb = sb.state_batched(E0b, np.zeros((8, w.N, 2)))
         sb.step(stb, w.steps)
