@@ -1,11 +1,16 @@
 // K independent fields sharing one weight set (2D TMz, collocated, FP32).
+// Fields are stored [N][F][K] (K contiguous).  Three kernel designs:
 //
-// Fields are stored [N][F][K] (K contiguous).  A wavefront owns one node and
-// 64 consecutive fields: the node's stencil indices and weights are
-// wave-uniform (scalar loads, read once for all 64 fields) and every
-// neighbour gather is one contiguous 256-byte row.  The grid is persistent:
-// a fixed number of resident workgroups strides over (node, field-chunk)
-// items, so the same wavefront keeps streaming through neighbouring nodes.
+// * global gathers (k_hb, k_eb): a wavefront owns one node and 64
+//   consecutive fields; the node's stencil indices and weights are
+//   wave-uniform (scalar loads, read once for all 64 fields) and every
+//   neighbour gather is one contiguous 256-byte row.  The grid is
+//   persistent: a fixed number of resident workgroups strides over (node,
+//   field-chunk) items.
+// * LDS-staged, one (tile, field-slice) item per workgroup (k_hbl, k_ebl).
+// * LDS-staged and persistent, with staging wavefronts that fill a second
+//   LDS buffer while the others sum (k_bpers).
+//
 // The update is the eq. 19 step of the single-field kernels (Kolar-Pozun &
 // Kosec, arXiv 2508.18205, Section 5) with every operator summed as eq. 16
 // writes it, over the whole stencil with the centre's own weight, rather than
@@ -132,18 +137,19 @@ __global__ __launch_bounds__(256) void k_eb(BA a) {
 // Workgroup = one 128-node tile x one 16-field slice (512 threads; the halo
 // slice takes ~60 KB of LDS, so two workgroups share a CU and one stages
 // while the other sums).  It copies the slice of every halo node's rows (E,
-// Hx, Hy) into LDS, then 4 threads per node each update 4 fields; stencil positions (16-bit) and
-// weights come from the same tile-sliced packed arrays as the single-field
-// kernels (and the same halo lists), one 16-byte load per 4 slots shared by
-// the node's 4 threads.  The slices of one tile are consecutive workgroups,
-// so they meet the tile's weights in L2.
+// Hx, Hy) into LDS, then 4 threads per node each update 4 fields; stencil
+// positions (16-bit) and weights come from tile-sliced packed arrays laid out
+// as the single-field kernels' (halo lists built for 128-node tiles), one
+// 16-byte load per 4 slots shared by the node's 4 threads, and the centre
+// weights of eq. 16 from one 16-byte load per node.  The slices of one tile
+// are consecutive workgroups, so they meet the tile's weights in L2.
 struct BLA {
     const float* E;
     const float* H;
     float* out;
     const uint4* lidx;    // [tiles][Q8][64] x 8 u16 halo positions
     const int32_t* hpool;
-    const int32_t* hoff;  // [256-node tiles + 1]
+    const int32_t* hoff;  // [128-node workgroup tiles + 1]
     const float* wc;      // [tiles][C4][2][64][4]
     const float* wh;      // [tiles][V4][64][4]
     const float* w0;      // [N][4] centre weights (curl x, curl y, hyperviscosity)
