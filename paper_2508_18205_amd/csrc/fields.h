@@ -95,7 +95,24 @@ typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
 
-// four consecutive packed weights
+// Position of value u (0..3) of lane `lane` in a packed weight chunk block of
+// 64 lanes x 4 values.  FP32 is lane-major ([64][4]: one 16-byte load per
+// lane, a contiguous 1 KB per wavefront); FP64 is split into two halves
+// ([2][64][2]) so that each of a lane's two 16-byte loads is also part of one
+// contiguous 1 KB run per wavefront (lane-major FP64 would give each load a
+// 32-byte lane stride, touching every cache line of the block twice).
+template <typename TW>
+struct WChunk {
+    static constexpr int LS = 4;  // values between consecutive lanes
+    __host__ __device__ static constexpr int at(int lane, int u) { return lane * 4 + u; }
+};
+template <>
+struct WChunk<double> {
+    static constexpr int LS = 2;
+    __host__ __device__ static constexpr int at(int lane, int u) { return (u >> 1) * 128 + lane * 2 + (u & 1); }
+};
+
+// the four packed weights of a chunk at p (the block base plus lane * LS)
 __device__ __forceinline__ void ldw4(const float* p, float (&w)[4]) {
     const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
     w[0] = v.x;
@@ -105,7 +122,7 @@ __device__ __forceinline__ void ldw4(const float* p, float (&w)[4]) {
 }
 __device__ __forceinline__ void ldw4(const double* p, double (&w)[4]) {
     const nt_d2 a = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
-    const nt_d2 b = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p) + 1);
+    const nt_d2 b = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p + 128));
     w[0] = a.x;
     w[1] = a.y;
     w[2] = b.x;
@@ -121,8 +138,8 @@ __device__ __forceinline__ void ldw4p(const float* p, float (&w)[4]) {
     w[3] = v.w;
 }
 __device__ __forceinline__ void ldw4p(const double* p, double (&w)[4]) {
-    const double2 a = reinterpret_cast<const double2*>(p)[0];
-    const double2 b = reinterpret_cast<const double2*>(p)[1];
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 128);
     w[0] = a.x;
     w[1] = a.y;
     w[2] = b.x;

@@ -871,7 +871,7 @@ __global__ void k_pack_cross(const int32_t* stc, const int32_t* sth, const doubl
             for (int u = 0; u < 4; ++u) {
                 const int s = 1 + 4 * q + u;
                 const double w = (real && s < n) ? wc[(ic * d + ax) * n + s] : 0.0;
-                pwc[(((tile * C4 + q) * d + ax) * RBFFD_TILE + lane) * 4 + u] = (TW)w;
+                pwc[((tile * C4 + q) * d + ax) * RBFFD_TILE * 4 + WChunk<TW>::at(lane, u)] = (TW)w;
             }
     }
     for (int q = 0; q < V4; ++q) {
@@ -880,7 +880,7 @@ __global__ void k_pack_cross(const int32_t* stc, const int32_t* sth, const doubl
             const int s = 1 + 4 * q + u;
             v[u] = (real && s < nh) ? sth[ic * nh + s] : (int)ic;
             const double w = (real && s < nh) ? wh[ic * nh + s] : 0.0;
-            pwh[((tile * V4 + q) * RBFFD_TILE + lane) * 4 + u] = (TW)w;
+            pwh[(tile * V4 + q) * RBFFD_TILE * 4 + WChunk<TW>::at(lane, u)] = (TW)w;
         }
         pidx_h[(tile * V4 + q) * RBFFD_TILE + lane] = make_int4(v[0], v[1], v[2], v[3]);
     }

@@ -263,8 +263,8 @@ __global__ __launch_bounds__(512) void k_h2x(SA<TS, TW> a) {
     TC dx = 0, dy = 0, vx = 0, vy = 0;
     const int4* pi = a.idx + tile * a.C4 * RBFFD_TILE + lane;
     const int4* pj = a.idx_h + tile * a.V4 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 2 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
     for (int q = 0; q < a.C4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4];
@@ -321,8 +321,8 @@ __global__ __launch_bounds__(512) void k_e2x(SA<TS, TW> a) {
     TC cu = 0, ve = 0;
     const int4* pi = a.idx + tile * a.C4 * RBFFD_TILE + lane;
     const int4* pj = a.idx_h + tile * a.V4 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 2 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 2 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
     for (int q = 0; q < a.C4; ++q) {
         const int4 j = pi[q * RBFFD_TILE];
         TW wx[4], wy[4];
@@ -490,8 +490,8 @@ __global__ __launch_bounds__(512) void k_h3(SA<TS, TW> a) {
     // d_a E_c accumulators for the curl
     TC xEy = 0, xEz = 0, yEx = 0, yEz = 0, zEx = 0, zEy = 0, vx = 0, vy = 0, vz = 0;
     const int4* pi = a.idx + tile * a.S4 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 3 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 3 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
     const int qb = min(a.C4, a.V4);
     int q = 0;
     for (; q < qb; ++q) {
@@ -567,8 +567,8 @@ __global__ __launch_bounds__(512) void k_e3(SA<TS, TW> a) {
     S::ld3(a.H, ic, hx0, hy0, hz0);
     TC xHy = 0, xHz = 0, yHx = 0, yHz = 0, zHx = 0, zHy = 0, vx = 0, vy = 0, vz = 0;
     const int4* pi = a.idx + tile * a.S4 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 3 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 3 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
     const int qb = min(a.C4, a.V4);
     int q = 0;
     for (; q < qb; ++q) {
@@ -946,8 +946,8 @@ __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
     S::ld3(a.H, ic, hx0, hy0, hz0);
     TC xEy = 0, xEz = 0, yEx = 0, yEz = 0, zEx = 0, zEy = 0, vx = 0, vy = 0, vz = 0;
     const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 3 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 3 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
     const int qm = max(a.C4, a.V4);
     // chunk q + 1 is loaded while chunk q is summed
     uint4 li = ldu4s(pl);
@@ -1024,8 +1024,8 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
     S::ld3(a.H, ic, hx0, hy0, hz0);
     TC xHy = 0, xHz = 0, yHx = 0, yHz = 0, zHx = 0, zHy = 0, vx = 0, vy = 0, vz = 0;
     const uint4* pl = a.lidx + tile * a.Q8 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tile * a.C4 * 3 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tile * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tile * a.C4 * 3 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
     const int qm = max(a.C4, a.V4);
     uint4 li = ldu4s(pl);
     TW nx[4] = {0, 0, 0, 0}, ny[4] = {0, 0, 0, 0}, nz[4] = {0, 0, 0, 0}, nh[4] = {0, 0, 0, 0};
@@ -1172,8 +1172,8 @@ __global__ __launch_bounds__(256) void k_h3p(SA<TS, TW> a) {
     S::ld3(a.H, ic, h0v[0], h0v[1], h0v[2]);
     TC c[6] = {0, 0, 0, 0, 0, 0}, v[3] = {0, 0, 0};
     const uint4* pl = a.lidx + tl * a.Q8 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tl * a.C4 * 3 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tl * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tl * a.C4 * 3 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    const TW* ph = a.wh + tl * a.V4 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
     stage_vec3<TS>(a.E, a.hpool + h0, hc, sF);
     __syncthreads();
     if (live) curl_sums3<TC, TW>(sF, pl, pc, a.C4, e0, c);
@@ -1207,8 +1207,8 @@ __global__ __launch_bounds__(256) void k_e3p(SA<TS, TW> a) {
     S::ld3(a.H, ic, h0v[0], h0v[1], h0v[2]);
     TC c[6] = {0, 0, 0, 0, 0, 0}, v[3] = {0, 0, 0};
     const uint4* pl = a.lidx + tl * a.Q8 * RBFFD_TILE + lane;
-    const TW* pc = a.wc + (tl * a.C4 * 3 * RBFFD_TILE + lane) * 4;
-    const TW* ph = a.wh + (tl * a.V4 * RBFFD_TILE + lane) * 4;
+    const TW* pc = a.wc + tl * a.C4 * 3 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    const TW* ph = a.wh + tl * a.V4 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
     stage_vec3<TS>(a.H, a.hpool + h0, hc, sF);
     __syncthreads();
     if (live) curl_sums3<TC, TW>(sF, pl, pc, a.C4, h0v, c);

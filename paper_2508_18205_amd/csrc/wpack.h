@@ -1,8 +1,9 @@
 // Packed weight chunks: how the step kernels store and read the weights of
 // 4 consecutive stencil slots of one lane.
 //
-// FP64 / FP32: the 4 values, lane-major ([tile][chunk][64][4]); one 16-byte
-// (FP32) or two 16-byte (FP64) loads per lane.
+// FP32: the 4 values, lane-major ([tile][chunk][64][4]), one 16-byte load
+// per lane; FP64: the 4 values in two halves ([tile][chunk][2][64][2]), two
+// 16-byte loads per lane, each reading a contiguous 1 KB per wavefront.
 //
 // W22 (compressed FP32 weights): 12 bytes per chunk -- four 22-bit signed
 // integer mantissas m_u and one 8-bit exponent b shared by the chunk; the
@@ -31,11 +32,11 @@ template <typename TW>
 struct WF {
     using V = TW;                      // value type the kernels compute with
     static constexpr int CH = 256;     // TW elements per (tile, chunk) block
-    static constexpr int LS = 4;       // TW elements between consecutive lanes
+    static constexpr int LS = WChunk<TW>::LS;  // TW elements between consecutive lanes
     __device__ __forceinline__ static void ld(const TW* p, V (&w)[4]) { ldw4(p, w); }
     __device__ __forceinline__ static void ldp(const TW* p, V (&w)[4]) { ldw4p(p, w); }
     __device__ __forceinline__ static void store(TW* p, const double (&w)[4]) {
-        for (int u = 0; u < 4; ++u) p[u] = (TW)w[u];
+        for (int u = 0; u < 4; ++u) p[WChunk<TW>::at(0, u)] = (TW)w[u];
     }
 };
 
