@@ -190,45 +190,45 @@ __device__ __forceinline__ int posq(const uint4& v, int half, int u) {
     return (int)((u & 1) ? (w >> 16) : (w & 0xFFFFu));
 }
 
-// The slice of every halo row (E, Hx, Hy) into LDS.  Item it of the slice
-// is piece q = it % Q of row (k, c) = divmod(it / Q, 3), and the LDS layout
-// [k][c][KSL] puts it at it * 4 floats.  Each round a thread takes SB items:
-// all their list values are loaded, then all their 16-byte field pieces, then
-// the LDS stores, so that the loads are in flight together.  Threads t of nt
-// take part (the whole workgroup, or its staging wavefronts).
+// The slice of every halo node's rows (E, Hx, Hy) into LDS, laid out
+// [k][c][KSL].  Thread t of nt (the whole workgroup, or its staging
+// wavefronts; nt a multiple of the Q 16-byte pieces per row) copies piece
+// q = t % Q of the three rows of halo nodes t / Q, t / Q + nt / Q, ...; each
+// round it loads the list values of NB nodes, then their 3 NB pieces, then
+// stores them, so that the loads are in flight together.
 template <int KSL>
 __device__ __forceinline__ void stage_slice(const BLA& a, float* sm, int64_t tile, int ks, int t, int nt) {
-    constexpr int SB = KSL == 4 ? 4 : 8;
-    constexpr int Q = KSL / 4;            // 16-byte pieces per row slice (1, 2 or 4)
-    constexpr int LQ = Q == 4 ? 2 : (Q == 2 ? 1 : 0);
+    constexpr int Q = KSL / 4;
+    constexpr int NB = 3;
     const int h0 = a.hoff[tile], hc = a.hoff[tile + 1] - h0;
-    const int K = a.K;
-    const int items = hc * 3 * Q;
-    const float* E = a.E + ks * KSL;
-    const float* H = a.H + ks * KSL;
-    for (int base = 0; base < items; base += SB * nt) {
-        int j[SB];
+    const uint64_t K = (uint32_t)a.K;
+    const int q = t & (Q - 1), step = nt / Q;
+    const float* E = a.E + ks * KSL + q * 4;
+    const float* H = a.H + ks * KSL + q * 4;
+    float* dst = sm + q * 4;
+    for (int base = t / Q; base < hc; base += NB * step) {
+        int j[NB];
 #pragma unroll
-        for (int b = 0; b < SB; ++b) {
-            const int it = base + b * nt + t;
-            j[b] = it < items ? a.hpool[h0 + (int)((unsigned)(it >> LQ) / 3u)] : -1;
+        for (int b = 0; b < NB; ++b) {
+            const int k = base + b * step;
+            j[b] = k < hc ? a.hpool[h0 + k] : -1;
         }
-        f4 v[SB];
+        f4 v[NB][3];
 #pragma unroll
-        for (int b = 0; b < SB; ++b) {
+        for (int b = 0; b < NB; ++b) {
             if (j[b] < 0) continue;
-            const int it = base + b * nt + t;
-            const unsigned row = (unsigned)it >> LQ, q = (unsigned)it & (Q - 1);
-            const unsigned c = row - 3u * (row / 3u);
-            // row of the source array: E[j] or H[j][c - 1] (32-bit index, 64-bit offset)
-            const unsigned r = c == 0 ? (unsigned)j[b] : 2u * (unsigned)j[b] + c - 1u;
-            const float* src = (c == 0 ? E : H) + (uint64_t)r * (uint32_t)K + q * 4;
-            v[b] = ldf4(src);
+            const uint64_t r = (uint32_t)j[b];
+            v[b][0] = ldf4(E + r * K);
+            v[b][1] = ldf4(H + 2 * r * K);
+            v[b][2] = ldf4(H + (2 * r + 1) * K);
         }
 #pragma unroll
-        for (int b = 0; b < SB; ++b) {
+        for (int b = 0; b < NB; ++b) {
             if (j[b] < 0) continue;
-            stf4(sm + (base + b * nt + t) * 4, v[b]);
+            float* d = dst + (base + b * step) * 3 * KSL;
+            stf4(d, v[b][0]);
+            stf4(d + KSL, v[b][1]);
+            stf4(d + 2 * KSL, v[b][2]);
         }
     }
 }
@@ -382,6 +382,34 @@ __device__ __forceinline__ void e_sum_full(const EChunk& c, const f4& wx, const 
     for (int u = 0; u < 4; ++u) fma4(ve, whs[u], c.e[u]);
 }
 
+// Chunks with hyperviscosity slots only (past the curl stencil): their LDS
+// reads and sums, and a branch-free loop over their pairs from an even chunk.
+template <int KSL, int HF>
+__device__ __forceinline__ void hv_h(const float* sm, uint4 lp, int fq, const f4& wh, f4& vx, f4& vy) {
+    f4 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int k = posq(lp, HF, u);
+        x[u] = ldf4(row<KSL>(sm, k, 1, fq));
+        y[u] = ldf4(row<KSL>(sm, k, 2, fq));
+    }
+    const float whs[4] = {wh.x, wh.y, wh.z, wh.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        fma4(vx, whs[u], x[u]);
+        fma4(vy, whs[u], y[u]);
+    }
+}
+template <int KSL, int HF>
+__device__ __forceinline__ void hv_e(const float* sm, uint4 lp, int fq, const f4& wh, f4& ve) {
+    f4 e[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) e[u] = ldf4(row<KSL>(sm, posq(lp, HF, u), 0, fq));
+    const float whs[4] = {wh.x, wh.y, wh.z, wh.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) fma4(ve, whs[u], e[u]);
+}
+
 // H update of one (tile, slice) item from its staged halo slice sm, by
 // thread tid of the tile's RBFFD_WGT_BATCH * TPN
 template <int TPN>
@@ -428,8 +456,16 @@ __device__ __forceinline__ void h_item(const BLA& a, const float* sm, int64_t ti
             lp = lpn;
         }
     }
-    // the rest: an odd last chunk with both parts, then the chunks past the
-    // shorter part
+    // pairs of hyperviscosity-only chunks, then the rest: an odd chunk with
+    // both parts, or the chunks past the shorter part
+    if (q == qb && !(q & 1) && a.V4 > a.C4) {
+        for (; q + 2 <= a.V4; q += 2) {
+            const uint4 lp = pl[(q >> 1) * RBFFD_TILE];
+            const f4 w0 = ldf4(ph + q * RBFFD_TILE * 4), w1 = ldf4(ph + (q + 1) * RBFFD_TILE * 4);
+            hv_h<KSL, 0>(sm, lp, fq, w0, vx, vy);
+            hv_h<KSL, 1>(sm, lp, fq, w1, vx, vy);
+        }
+    }
     for (; q < qm; ++q) {
         f4 zx{0, 0, 0, 0}, zy{0, 0, 0, 0}, zh{0, 0, 0, 0};
         w_read(a, q, pc, ph, zx, zy, zh);
@@ -487,6 +523,14 @@ __device__ __forceinline__ void e_item(const BLA& a, const float* sm, int64_t ti
             e_read_full<KSL, 1>(sm, lp, fq, A);
             e_sum_full(A, wx1, wy1, wh1, cu, ve);
             lp = lpn;
+        }
+    }
+    if (q == qb && !(q & 1) && a.V4 > a.C4) {
+        for (; q + 2 <= a.V4; q += 2) {
+            const uint4 lp = pl[(q >> 1) * RBFFD_TILE];
+            const f4 w0 = ldf4(ph + q * RBFFD_TILE * 4), w1 = ldf4(ph + (q + 1) * RBFFD_TILE * 4);
+            hv_e<KSL, 0>(sm, lp, fq, w0, ve);
+            hv_e<KSL, 1>(sm, lp, fq, w1, ve);
         }
     }
     for (; q < qm; ++q) {
