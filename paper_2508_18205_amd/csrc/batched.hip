@@ -148,6 +148,7 @@ struct BLA {
     const float* H;
     float* out;
     const uint4* lidx;    // [tiles][Q8][64] x 8 u16 halo positions
+    const uint16_t* lself;// [tiles * 64] each node's own halo position
     const int32_t* hpool;
     const int32_t* hoff;  // [128-node workgroup tiles + 1]
     const float* wc;      // [tiles][C4][2][64][4]
@@ -422,7 +423,9 @@ __device__ __forceinline__ void h_item(const BLA& a, const float* sm, int64_t ti
     const int ln = (int)(i % RBFFD_TILE);
     const int64_t K = a.K;
     const int k0 = ks * KSL + fq * 4;
-    const f4 e0 = ldf4(a.E + i * K + k0), hx0 = ldf4(a.H + (i * 2) * K + k0), hy0 = ldf4(a.H + (i * 2 + 1) * K + k0);
+    // the node's own values, from its row of the staged slice
+    const int sp = a.lself[i];
+    const f4 e0 = ldf4(row<KSL>(sm, sp, 0, fq)), hx0 = ldf4(row<KSL>(sm, sp, 1, fq)), hy0 = ldf4(row<KSL>(sm, sp, 2, fq));
     // the centre's own terms of eq. 16 first
     const f4 c0 = ldf4(a.w0 + i * 4);
     f4 dx = mul4(c0.x, e0), dy = mul4(c0.y, e0), vx = mul4(c0.z, hx0), vy = mul4(c0.z, hy0);
@@ -495,7 +498,9 @@ __device__ __forceinline__ void e_item(const BLA& a, const float* sm, int64_t ti
     const int ln = (int)(i % RBFFD_TILE);
     const int64_t K = a.K;
     const int k0 = ks * KSL + fq * 4;
-    const f4 e0 = ldf4(a.E + i * K + k0), hx0 = ldf4(a.H + (i * 2) * K + k0), hy0 = ldf4(a.H + (i * 2 + 1) * K + k0);
+    // the node's own values, from its row of the staged slice
+    const int sp = a.lself[i];
+    const f4 e0 = ldf4(row<KSL>(sm, sp, 0, fq)), hx0 = ldf4(row<KSL>(sm, sp, 1, fq)), hy0 = ldf4(row<KSL>(sm, sp, 2, fq));
     const f4 c0 = ldf4(a.w0 + i * 4);
     f4 cu = mul4(c0.x, hy0), ve = mul4(c0.z, e0);
     fms4(cu, c0.y, hx0);
@@ -654,6 +659,7 @@ void launch_half_staged(const rbffd_plan* p, const rbffd_fields* f, int c, bool 
     const int ksl = 4 * tpn;
     BLA a{};
     a.lidx = (const uint4*)ob.lidx;
+    a.lself = ob.lself;
     a.hpool = ob.hpool;
     a.hoff = ob.hoff;
     a.wc = (const float*)ob.pwc;

@@ -60,6 +60,7 @@ struct OpBlock {
     // source nodes of all its stencils ("halo list") and, per node and slot,
     // the 16-bit position of the slot's node in that list
     uint16_t* lidx = nullptr;      // [tiles][Q8][64][8]
+    uint16_t* lself = nullptr;     // [tiles * 64] each node's own position (K-field batch)
     int32_t* hpool = nullptr;      // concatenated halo lists
     int32_t* hoff = nullptr;       // [nwg + 1] start of each workgroup's list
     int32_t Q8 = 0;

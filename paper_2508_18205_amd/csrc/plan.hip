@@ -97,6 +97,7 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int cb, int K, bool adjo
         o.wgt = K > 1 ? RBFFD_WGT_BATCH : RBFFD_WGT;
         o.nwg = cdiv(o.tiles, o.wgt / RBFFD_TILE);
         o.lidx = b.take<uint16_t>(T * o.Q8 * 8);
+        if (K > 1) o.lself = b.take<uint16_t>(T);
         o.hpool = b.take<int32_t>(o.Nt * o.ns);
         o.hoff = b.take<int32_t>(o.nwg + 1);
     } else {

@@ -1024,7 +1024,7 @@ __device__ __forceinline__ int lower_pos(const int32_t* a, int n, int32_t v) {
 }
 
 __global__ void k_hlocal(const int32_t* st, int64_t N, int ns, const int32_t* pool, const int32_t* hoff, int Q8,
-                         int64_t tiles, int tsz, uint16_t* lidx) {
+                         int64_t tiles, int tsz, uint16_t* lidx, uint16_t* lself) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= tiles * RBFFD_TILE) return;
     const int64_t tile = g / RBFFD_TILE;
@@ -1034,6 +1034,7 @@ __global__ void k_hlocal(const int32_t* st, int64_t N, int ns, const int32_t* po
     const int32_t* L = pool + hoff[wg];
     const int cnt = hoff[wg + 1] - hoff[wg];
     const int self = real ? lower_pos(L, cnt, (int32_t)g) : 0;
+    if (lself) lself[g] = (uint16_t)self;
     for (int q = 0; q < Q8; ++q)
         for (int u = 0; u < 8; ++u) {
             const int s = 1 + 8 * q + u;
@@ -1593,7 +1594,7 @@ int build_halos(rbffd_plan* p, void* wsp, hipStream_t st) {
     HIPCHK(p, rocprim::exclusive_scan(stemp, sb, flag, pos, (int32_t)0, (size_t)E, rocprim::plus<int32_t>(), st));
     hipLaunchKernelGGL(k_hcompact, dim3(blocks(E)), dim3(256), 0, st, kout, flag, pos, E, o.hpool, o.hoff, o.nwg);
     hipLaunchKernelGGL(k_hlocal, dim3(blocks(o.tiles * RBFFD_TILE)), dim3(256), 0, st, o.st_union, N, (int)ns,
-                       o.hpool, o.hoff, o.Q8, o.tiles, tsz, o.lidx);
+                       o.hpool, o.hoff, o.Q8, o.tiles, tsz, o.lidx, o.lself);
     HIPCHK(p, hipGetLastError());
     std::vector<int32_t> off(o.nwg + 1);
     HIPCHK(p, hipMemcpyAsync(off.data(), o.hoff, (o.nwg + 1) * 4, hipMemcpyDeviceToHost, st));
