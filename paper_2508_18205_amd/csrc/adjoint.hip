@@ -30,7 +30,8 @@ struct AA {
     const int64_t* toff;
     const int32_t* twidth;
     const int32_t* tsrc;
-    const T* tw;          // [e][4]
+    const T* tw;          // [3][tcap]: D^dx, D^dy, D^hv weights of each entry
+    int64_t tcap;
     double a, g, dt, eps0;
     const void* eps_r;
     const uint8_t* emask;
@@ -83,9 +84,9 @@ __global__ void k_adj2(AA<T> a) {
         const int64_t e = base + (int64_t)q * 64;
         const int32_t i = a.tsrc[e];
         const T km = a.kmu[i];
-        sx += a.tw[e * 4 + 0] * km;
-        sy += a.tw[e * 4 + 1] * km;
-        sh += a.tw[e * 4 + 2] * km;
+        sx += a.tw[e] * km;
+        sy += a.tw[a.tcap + e] * km;
+        sh += a.tw[2 * a.tcap + e] * km;
     }
     if (j >= a.N) return;
     a.lhat[j * 2 + 0] = a.lamH[j * 2 + 0] - sy;
@@ -108,7 +109,7 @@ __global__ void k_adj3(AA<T> a) {
         const int64_t e = base + (int64_t)q * 64;
         const int32_t i = a.tsrc[e];
         const T lx = a.lhat[(int64_t)i * 2 + 0], ly = a.lhat[(int64_t)i * 2 + 1];
-        const T wx = a.tw[e * 4 + 0], wy = a.tw[e * 4 + 1], wh = a.tw[e * 4 + 2];
+        const T wx = a.tw[e], wy = a.tw[a.tcap + e], wh = a.tw[2 * a.tcap + e];
         ce += -wy * lx + wx * ly;
         hx += wh * lx;
         hy += wh * ly;
@@ -219,6 +220,7 @@ int adjoint_impl(const rbffd_plan* p, const rbffd_fields* f, const rbffd_adjoint
     a.twidth = o.t_width;
     a.tsrc = o.t_src;
     a.tw = (const T*)o.t_w;
+    a.tcap = o.t_cap;
     a.a = p->dt / p->p.mu0;
     a.g = p->gamma;
     a.dt = p->dt;

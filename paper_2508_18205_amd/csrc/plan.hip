@@ -125,7 +125,7 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int cb, int K, bool adjo
         o.t_cap = T * 6 * (int64_t)o.ns;
         o.t_src = b.take<int32_t>(o.t_cap);
         o.t_slot = b.take<int32_t>(o.t_cap);
-        o.t_w = b.take_bytes(o.t_cap * 4 * wb);
+        o.t_w = b.take_bytes(o.t_cap * 3 * wb);   // [3][t_cap]: D^dx, D^dy, D^hv weights
     }
 }
 }  // namespace

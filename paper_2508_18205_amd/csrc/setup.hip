@@ -971,16 +971,17 @@ __global__ void k_tfill(const uint64_t* skeys, const int32_t* rstart, const int3
 
 // transposed weights (wx, wy, wh, 0) of every SELL entry from the FP64 weights
 template <typename TW>
+// the transposed weights of each entry, one array per operator ([3][cap]:
+// D^dx, D^dy, D^hv) so that a wavefront's load of one of them is contiguous
 __global__ void k_tweights(const int32_t* tsrc, const int32_t* tslot, int64_t E, const double* wc, const double* wh,
-                           int n, int nh, TW* tw) {
+                           int n, int nh, int64_t cap, TW* tw) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
     const int s = tslot[e];
     const int64_t i = tsrc[e];
-    tw[e * 4 + 0] = (TW)((s >= 0 && s < n) ? wc[(i * 2 + 0) * n + s] : 0.0);
-    tw[e * 4 + 1] = (TW)((s >= 0 && s < n) ? wc[(i * 2 + 1) * n + s] : 0.0);
-    tw[e * 4 + 2] = (TW)((s >= 0 && s < nh) ? wh[i * nh + s] : 0.0);
-    tw[e * 4 + 3] = (TW)0.0;
+    tw[e] = (TW)((s >= 0 && s < n) ? wc[(i * 2 + 0) * n + s] : 0.0);
+    tw[cap + e] = (TW)((s >= 0 && s < n) ? wc[(i * 2 + 1) * n + s] : 0.0);
+    tw[2 * cap + e] = (TW)((s >= 0 && s < nh) ? wh[i * nh + s] : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1629,10 +1630,10 @@ int refill_transpose(rbffd_plan* p, hipStream_t st) {
     if (E <= 0) return RBFFD_OK;
     if (p->p.wdtype == RBFFD_F64)
         hipLaunchKernelGGL(k_tweights<double>, dim3(blocks(E)), dim3(256), 0, st, o.t_src, o.t_slot, E, o.wc, o.wh,
-                           o.n, o.nh, (double*)o.t_w);
+                           o.n, o.nh, o.t_cap, (double*)o.t_w);
     else
         hipLaunchKernelGGL(k_tweights<float>, dim3(blocks(E)), dim3(256), 0, st, o.t_src, o.t_slot, E, o.wc, o.wh,
-                           o.n, o.nh, (float*)o.t_w);
+                           o.n, o.nh, o.t_cap, (float*)o.t_w);
     HIPCHK(p, hipGetLastError());
     p->opE = p->opH;
     return RBFFD_OK;
