@@ -141,8 +141,9 @@ __global__ __launch_bounds__(256) void k_eb(BA a) {
 // positions (16-bit) and weights come from tile-sliced packed arrays laid out
 // as the single-field kernels' (halo lists built for 128-node tiles), one
 // 16-byte load per 4 slots shared by the node's 4 threads, and the centre
-// weights of eq. 16 from one 16-byte load per node.  The slices of one tile
-// are consecutive workgroups, so they meet the tile's weights in L2.
+// weights of eq. 16 from one 16-byte load per node; the node's own values
+// come from its row of the staged slice.  The slices of one tile are
+// consecutive workgroups, so they meet the tile's weights in L2.
 struct BLA {
     const float* E;
     const float* H;
