@@ -1,6 +1,7 @@
 /*
  * Plain FP64 stabilised leapfrog (Kolar-Pozun & Kosec, arXiv 2508.18205,
- * Section 5, eq. 19) for the 2D TMz fields, one half update per call.
+ * Section 5, eq. 19) for the 2D TMz fields and for 3D, one half update per
+ * call.
  *
  * TEST INFRASTRUCTURE ONLY: part of the CPU oracle.  Only the tests, the
  * package smoke check and the CPU-baseline leg of the benchmark may call it.
@@ -69,6 +70,57 @@ void oracle_e_update_tm(int64_t N, const double* E, const double* Hn, double* Eo
         const double k = kappa ? kappa[i] : kappa0;
         const double br = dxHy - dyHx + gamma * hv;
         Eout[i] = (E[i] + k * br) * keep[i];
+    }
+}
+
+/*
+ * 3D: the full discrete curl of eq. 19, E [N][3], H [N][3] (x, y, z), curl
+ * weights cw [N][3][n] (D^dx, D^dy, D^dz rows), with
+ *   curl F = (D^dy Fz - D^dz Fy, D^dz Fx - D^dx Fz, D^dx Fy - D^dy Fx)
+ *   H_c <- H_c - a (curl_c E - gamma D^hv H_c)
+ *   E_c <- keep_ic (E_c + kappa_i (curl_c H_new + gamma D^hv E_c))
+ * keep [N][3]: 0 for an E component tangential to a PEC wall at the node.
+ */
+static void curl3(const double* cw, const int64_t* c, int n, const double* F, double out[3]) {
+    const double* wx = cw;
+    const double* wy = cw + n;
+    const double* wz = cw + 2 * n;
+    const double dyFz = dsum(wy, c, n, F, 3, 2), dzFy = dsum(wz, c, n, F, 3, 1);
+    const double dzFx = dsum(wz, c, n, F, 3, 0), dxFz = dsum(wx, c, n, F, 3, 2);
+    const double dxFy = dsum(wx, c, n, F, 3, 1), dyFx = dsum(wy, c, n, F, 3, 0);
+    out[0] = dyFz - dzFy;
+    out[1] = dzFx - dxFz;
+    out[2] = dxFy - dyFx;
+}
+
+/* H^{n+1} from E^n and H^n (3D). */
+void oracle_h_update_3d(int64_t N, const double* E, const double* H, double* Hout, int n, const int64_t* ci,
+                        const double* cw, int nh, const int64_t* hi, const double* hw, double a, double gamma) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double cu[3];
+        curl3(cw + i * 3 * n, ci + i * n, n, E, cu);
+        for (int c = 0; c < 3; ++c) {
+            const double hv = nh > 0 ? dsum(hw + i * nh, hi + i * nh, nh, H, 3, c) : 0.0;
+            Hout[3 * i + c] = H[3 * i + c] - a * (cu[c] - gamma * hv);
+        }
+    }
+}
+
+/* E^{n+1} from E^n and H^{n+1} (3D), then the PEC factors.  kappa: [N]
+ * per-node values, or NULL to use kappa0 everywhere. */
+void oracle_e_update_3d(int64_t N, const double* E, const double* Hn, double* Eout, int n, const int64_t* ci,
+                        const double* cw, int nh, const int64_t* hi, const double* hw, const double* kappa,
+                        double kappa0, double gamma, const double* keep) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double cu[3];
+        curl3(cw + i * 3 * n, ci + i * n, n, Hn, cu);
+        const double k = kappa ? kappa[i] : kappa0;
+        for (int c = 0; c < 3; ++c) {
+            const double hv = nh > 0 ? dsum(hw + i * nh, hi + i * nh, nh, E, 3, c) : 0.0;
+            Eout[3 * i + c] = (E[3 * i + c] + k * (cu[c] + gamma * hv)) * keep[3 * i + c];
+        }
     }
 }
 

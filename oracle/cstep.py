@@ -1,9 +1,9 @@
 """Loader of the oracle's plain C leapfrog (oracle/cstep.c) for large node sets.
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  The C file computes the
-same 2D TMz half updates as ``oracle.step.h_update`` / ``e_update`` (eq. 19)
-with a loop over nodes (OpenMP over nodes, no fused multiply-adds); this
-module only marshals arrays and runs the step loop.  ``build`` compiles it
+same 2D TMz and 3D half updates as ``oracle.step.h_update`` / ``e_update``
+(eq. 19) with a loop over nodes (OpenMP over nodes, no fused multiply-adds);
+this module only marshals arrays and runs the step loop.  ``build`` compiles it
 with gcc; ``load`` builds it when it is missing.
 """
 import ctypes as C
@@ -45,6 +45,11 @@ def load():
     lib.oracle_e_update_tm.restype = None
     lib.oracle_e_update_tm.argtypes = [C.c_int64, P, P, P, C.c_int, P, P, C.c_int, P, P, P, C.c_double, C.c_double,
                                        P]
+    for nm in ("oracle_h_update_3d",):
+        getattr(lib, nm).restype = None
+        getattr(lib, nm).argtypes = lib.oracle_h_update_tm.argtypes
+    lib.oracle_e_update_3d.restype = None
+    lib.oracle_e_update_3d.argtypes = lib.oracle_e_update_tm.argtypes
     lib.oracle_threads.restype = C.c_int
     lib.oracle_threads.argtypes = []
     lib.oracle_set_threads.restype = None
@@ -64,7 +69,8 @@ def set_threads(t):
 
 
 class Operator:
-    """Contiguous FP64 / int64 copies of an ``oracle.step`` operator dict (2D)."""
+    """Contiguous FP64 / int64 copies of an ``oracle.step`` operator dict
+    (2D or 3D, from the curl weights' shape)."""
 
     def __init__(self, op):
         self.ci = np.ascontiguousarray(op["curl_idx"], dtype=np.int64)
@@ -73,7 +79,8 @@ class Operator:
         self.hw = np.ascontiguousarray(op["hv_w"], dtype=np.float64)
         self.N, self.n = self.ci.shape
         self.nh = self.hi.shape[1] if self.hw.size else 0
-        assert self.cw.shape == (self.N, 2, self.n)
+        self.d = self.cw.shape[1]
+        assert self.cw.shape == (self.N, self.d, self.n) and self.d in (2, 3)
 
 
 def _p(a):
@@ -81,18 +88,21 @@ def _p(a):
 
 
 def h_update(E, H, op, a, gamma, out=None):
-    """H^{n+1} [N, 2] from E^n [N, 1] and H^n [N, 2]."""
+    """H^{n+1} from E^n and H^n: [N, 2] from [N, 1], [N, 2] in 2D TMz; [N, 3]
+    from [N, 3], [N, 3] in 3D."""
     lib = load()
     E = np.ascontiguousarray(E, dtype=np.float64)
     H = np.ascontiguousarray(H, dtype=np.float64)
     out = np.empty_like(H) if out is None else out
-    lib.oracle_h_update_tm(op.N, _p(E), _p(H), _p(out), op.n, _p(op.ci), _p(op.cw), op.nh, _p(op.hi),
-                           _p(op.hw), float(a), float(gamma))
+    fn = lib.oracle_h_update_3d if op.d == 3 else lib.oracle_h_update_tm
+    fn(op.N, _p(E), _p(H), _p(out), op.n, _p(op.ci), _p(op.cw), op.nh, _p(op.hi), _p(op.hw), float(a),
+       float(gamma))
     return out
 
 
 def e_update(E, Hn, op, kappa, gamma, keep, out=None):
-    """E^{n+1} [N, 1] from E^n and H^{n+1}; kappa scalar or [N]; keep [N] or [N, 1]."""
+    """E^{n+1} from E^n and H^{n+1} ([N, 1] in 2D TMz, [N, 3] in 3D); kappa
+    scalar or [N]; keep shaped like E (or [N] in 2D)."""
     lib = load()
     E = np.ascontiguousarray(E, dtype=np.float64)
     Hn = np.ascontiguousarray(Hn, dtype=np.float64)
@@ -104,25 +114,27 @@ def e_update(E, Hn, op, kappa, gamma, keep, out=None):
         k0 = float(kappa)
     else:
         karr = np.ascontiguousarray(kappa, dtype=np.float64)
-    lib.oracle_e_update_tm(op.N, _p(E), _p(Hn), _p(out), op.n, _p(op.ci), _p(op.cw), op.nh, _p(op.hi),
-                           _p(op.hw), _p(karr), k0, float(gamma), _p(keep))
+    assert keep.size == E.size
+    fn = lib.oracle_e_update_3d if op.d == 3 else lib.oracle_e_update_tm
+    fn(op.N, _p(E), _p(Hn), _p(out), op.n, _p(op.ci), _p(op.cw), op.nh, _p(op.hi), _p(op.hw), _p(karr), k0,
+       float(gamma), _p(keep))
     return out
 
 
 def run(E, H, op, dt, steps, gamma, kappa, keep, mu0=1.0, eps0=1.0, h=None, energy_every=0, callback=None):
-    """``oracle.step.run`` for the collocated 2D TMz field without sources:
-    returns (E, H, energies).  callback(n, E, H), if given, sees the state
-    after each step n = 1 .. steps."""
+    """``oracle.step.run`` for a collocated field without sources (2D TMz or
+    3D): returns (E, H, energies).  callback(n, E, H), if given, sees the
+    state after each step n = 1 .. steps."""
     a = dt / mu0
     eta0 = math.sqrt(mu0 / eps0)
-    E = np.array(E, dtype=np.float64).reshape(-1, 1)
+    E = np.array(E, dtype=np.float64).reshape(op.N, -1)
     H = np.array(H, dtype=np.float64)
     E2, H2 = np.empty_like(E), np.empty_like(H)
     energies = []
     for n in range(steps):
         h_update(E, H, op, a, gamma, out=H2)
         if energy_every and n % energy_every == 0:
-            energies.append(_step.energy(E, H, H2, h, h, eta0, 2))
+            energies.append(_step.energy(E, H, H2, h, h, eta0, op.d))
         e_update(E, H2, op, kappa, gamma, keep, out=E2)
         E, E2 = E2, E
         H, H2 = H2, H

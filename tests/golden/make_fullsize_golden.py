@@ -13,6 +13,9 @@ tests/test_gpu_fullsize_parity.py and by the benchmark:
                       first leaves [0, 1.01] near step 7000)
   pulse2d_1M_a2.npz   the same nodes and curl stencils with alpha = 2
                       (n_hv = 31), chat = 3e-3, 10^4 steps (energy-stable)
+  tm111_3d_8M.npz     the 3D cube: 200^3 jittered nodes on the PEC unit cube,
+                      n = 35, m = 2, alpha = 2 (n_hv = 71), chat = 1e-3, the
+                      TM_111 mode, 2000 steps
 
 Each file holds: the sampled node ids (original order) and the oracle's E
 [S, 1], H [S, 2] there after the last step; the energy U^n of eq. 20 every
@@ -21,8 +24,8 @@ each full field component on 8 seeded standard normal vectors g_j (numpy
 default_rng(seed 2508) drawn as [8, N]), which turn any widespread
 difference into a global relative L2 estimate; and the run's parameters.
 
-Usage:  python tests/golden/make_fullsize_golden.py [a3] [a2]
-(about 15 and 40 minutes on 8 cores).
+Usage:  python tests/golden/make_fullsize_golden.py [a3] [a2] [c3]
+(about 15, 40 and 75 minutes on 8 cores; c3 needs ~30 GB of memory).
 """
 import math
 import os
@@ -86,7 +89,49 @@ def run_one(tag, w, alpha, n_hv, chat, steps, energy_every, stencils, curl_w, sm
         f"[{(en / en[0]).min():.6f}, {(en / en[0]).max():.6f}]")
 
 
+def run_cube(procs=8):
+    """The 8M-node 3D cube (tm111_3d as the benchmark runs it), 2000 steps."""
+    from oracle import setup as osetup
+    t0 = time.time()
+    w = configs.tm111_3d(scale=1.0, chat=1e-3)
+    log(f"[c3] nodes: N={w.N} h={w.h:.4e} ({time.time() - t0:.0f} s)")
+    t0 = time.time()
+    stencils = knn.knn_cells(w.xyz, max(w.n, w.n_hv))
+    log(f"[c3] stencils (n_s = {stencils.shape[1]}) {time.time() - t0:.0f} s")
+    t0 = time.time()
+    curl_w, hv_w = osetup.weights_parallel(w.xyz, stencils, w.n, w.m, w.n_hv, w.alpha, procs)
+    log(f"[c3] weights {time.time() - t0:.0f} s")
+    op = cstep.Operator({"curl_idx": stencils[:, :w.n], "curl_w": curl_w, "hv_idx": stencils[:, :w.n_hv],
+                         "hv_w": hv_w})
+    del curl_w, hv_w
+    gamma = ostep.hv_gamma(w.hv_c, w.alpha, w.h)
+    keep = ostep.pec_keep(w.flags, 3)
+    steps, every = w.steps, 100
+    t0 = time.time()
+
+    def progress(n, E, H):
+        if n % 100 == 0:
+            log(f"[c3] step {n}/{steps} ({time.time() - t0:.0f} s)")
+
+    E, H, en = cstep.run(w.E0, w.H0, op, w.dt, steps, gamma, w.dt / w.eps0, keep, mu0=w.mu0, eps0=w.eps0, h=w.h,
+                         energy_every=every, callback=progress)
+    smp = sample_nodes(w, 33, 4000, 0, 0.0)
+    g = np.random.default_rng(PROJ_SEED).standard_normal((N_PROJ, w.N))
+    out = os.path.join(HERE, "tm111_3d_8M.npz")
+    np.savez_compressed(out, nodes=smp, E=E[smp], H=H[smp], energy=en, energy_every=every,
+                        projE=projections(E, g), projH=projections(H, g), N=w.N, steps=steps, alpha=w.alpha,
+                        n_hv=w.n_hv, chat=w.chat, n=w.n, m=w.m, proj_seed=PROJ_SEED,
+                        threads=cstep.threads(), run_s=time.time() - t0)
+    log(f"[c3] wrote {out}: {steps} steps in {time.time() - t0:.0f} s; u range "
+        f"[{(en / en[0]).min():.6f}, {(en / en[0]).max():.6f}]")
+
+
 def main(which):
+    if "c3" in which:
+        run_cube()
+        which = [x for x in which if x != "c3"]
+        if not which:
+            return
     t0 = time.time()
     w = configs.pulse_2d(scale=1.0)
     log(f"nodes: N={w.N} h={w.h:.4e} ({time.time() - t0:.0f} s)")

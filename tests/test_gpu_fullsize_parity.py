@@ -13,6 +13,9 @@ configuration the benchmark times (autotuned variant, HIP-graph replay).
   Bars: 1e-9 in FP64 (the two sides' weights differ by rounding of their
   own FP64 solves), 1e-5 in FP32, with FP32 weights and with the compressed
   W22 weights.
+* The 8.0M-node 3D cube (PEC unit cube, n = 35, m = 2, alpha = 2, TM_111
+  mode), 2000 steps end to end in FP64 and FP32 against the oracle's stored
+  FP64 run (tests/golden/tm111_3d_8M.npz), the same checks and bars.
 * The two-set variant at the 2D cavity's size (51^2 E nodes, 50^2 H nodes,
   TM_11, one period = 1000 steps), FP64 with injected oracle weights
   (1e-12) and end to end (1e-9), against the oracle run in the test.
@@ -88,6 +91,41 @@ def test_pulse_1M_end_to_end_vs_oracle(pulse, tag, precision):
     pE = np.stack([gv @ E[:, 0]])
     pH = np.stack([gv @ H[:, c] for c in range(2)])
     gE, gH = _proj_rel(pE, g["projE"]), _proj_rel(pH, g["projH"])
+    _announce(f"  variant {s.variant()}: sampled nodes ({nodes.size}) E {eE:.2e} H {eH:.2e}; energy {eU:.2e}; "
+              f"projections E {gE:.2e} H {gH:.2e}")
+    tol = 1e-9 if precision == "f64" else 1e-5
+    assert eE < tol and eH < tol
+    assert eU < tol
+    assert gE < tol and gH < tol
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_cube_8M_end_to_end_vs_oracle(precision):
+    path = os.path.join(GOLD, "tm111_3d_8M.npz")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/tm111_3d_8M.npz not written (tests/golden/make_fullsize_golden.py c3)")
+    g = np.load(path)
+    w = configs.tm111_3d(scale=1.0, chat=float(g["chat"]))
+    assert int(g["N"]) == w.N and (w.alpha, w.n_hv, w.n) == (int(g["alpha"]), int(g["n_hv"]), int(g["n"]))
+    steps, every = int(g["steps"]), int(g["energy_every"])
+    _announce(f"cube 8M {precision}: N={w.N} n={w.n} n_hv={w.n_hv} steps={steps}")
+    s = Solver.from_workload(w, precision=precision)
+    st = s.state(w.E0, w.H0)
+    s.autotune(st, reps=3)
+    st = s.state(w.E0, w.H0)
+    r = s.run(st, steps, energy_every=every, use_graph=True)
+    E, H = s.E_original(st), s.H_original(st)
+    # relative L2 over all three components together (H_z of the TM_111 mode
+    # is zero up to discretisation error, so it has no scale of its own)
+    nodes = g["nodes"]
+    eE = np.linalg.norm(E[nodes] - g["E"]) / np.linalg.norm(g["E"])
+    eH = np.linalg.norm(H[nodes] - g["H"]) / np.linalg.norm(g["H"])
+    eU = float(np.abs(r["energy"] / g["energy"] - 1.0).max())
+    gv = np.random.default_rng(int(g["proj_seed"])).standard_normal((g["projE"].shape[1], w.N))
+    pE = np.stack([gv @ E[:, c] for c in range(3)])
+    pH = np.stack([gv @ H[:, c] for c in range(3)])
+    gE = np.linalg.norm(pE - g["projE"]) / np.linalg.norm(g["projE"])
+    gH = np.linalg.norm(pH - g["projH"]) / np.linalg.norm(g["projH"])
     _announce(f"  variant {s.variant()}: sampled nodes ({nodes.size}) E {eE:.2e} H {eH:.2e}; energy {eU:.2e}; "
               f"projections E {gE:.2e} H {gH:.2e}")
     tol = 1e-9 if precision == "f64" else 1e-5

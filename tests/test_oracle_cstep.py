@@ -5,7 +5,8 @@ the cell-bucket stencil search (oracle.knn.knn_cells).
   (curl and hyperviscosity parts, eps0 != mu0), the same pins the numpy step
   satisfies, and agree with the numpy step to rounding on scattered nodes
   with PEC walls and per-node eps_r; a TM_11 cavity run converges to the
-  analytic mode as the numpy one does.
+  analytic mode as the numpy one does.  The same in 3D (full curl, PEC
+  factors per component) on a jittered cube.
 * knn_cells returns the brute-force stencils bit for bit: uniform, clustered
   and anisotropic sets, regular grids (distance ties everywhere), periodic
   boxes, centres drawn from another set, 2D and 3D.
@@ -95,6 +96,63 @@ def test_c_step_tm11_cavity_converges():
         errs.append(step.linf_errors(E, H, Ea, Ha)[0])
     order = math.log(errs[0] / errs[1]) / math.log(2.0)
     assert errs[1] < errs[0] and order > 0.8, (errs, order)
+
+
+def test_c_step_3d_polynomial_closed_forms():
+    xyz, flags, h = nodes.jittered_grid((8, 8, 8), seed=22)
+    N = xyz.shape[0]
+    idx = knn.knn(xyz, 71)
+    op = {"curl_idx": idx[:, :35], "curl_w": W.curl_weights(xyz, xyz, idx[:, :35], 2), "hv_idx": idx,
+          "hv_w": W.hv_weights(xyz, xyz, idx, 2)}
+    cop = cstep.Operator(op)
+    assert cop.d == 3
+    eps0, mu0, dt = 2.0, 0.5, 0.003
+    a, kappa = dt / mu0, dt / eps0
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    keep = step.pec_keep(flags, 3)
+    zero = np.zeros((N, 3))
+    # curl: E = (0, 0, x y) -> curl E = (x, -y, 0), H = -a curl E
+    E = np.stack([0 * x, 0 * x, x * y], axis=1)
+    H1 = cstep.h_update(E, zero, cop, a, 0.0)
+    assert np.abs(H1 - np.stack([-a * x, a * y, 0 * x], axis=1)).max() < 1e-11
+    # H = (0, 0, x z) -> curl H = (0, -z, 0); E1 = keep * (E + kappa curl H)
+    H = np.stack([0 * x, 0 * x, x * z], axis=1)
+    E1 = cstep.e_update(zero, H, cop, kappa, 0.0, keep)
+    assert np.abs(E1 - keep * np.stack([0 * x, -kappa * z, 0 * x], axis=1)).max() < 1e-11
+    # hyperviscosity: Delta^2 x^4 = 24, Delta^2 y^2 z^2 = 8, Delta^2 x^2 y z = 0
+    gamma = -0.7
+    xs, ys, zs = x - 0.3, y - 0.6, z - 0.4
+    H = np.stack([xs ** 4, ys * ys * zs * zs, xs * xs * ys * zs], axis=1)
+    H1 = cstep.h_update(zero, H, cop, a, gamma)
+    assert np.abs(H1 - (H + a * gamma * np.array([24.0, 8.0, 0.0]))).max() < 1e-8
+    E1 = cstep.e_update(H, zero, cop, kappa, gamma, keep)
+    assert np.abs(E1 - keep * (H + kappa * gamma * np.array([24.0, 8.0, 0.0]))).max() < 1e-8
+
+
+def test_c_step_3d_matches_numpy_step():
+    w = configs.tm111_3d(n_side=8, chat=1e-3)
+    oh, _ = setup.operators(w)
+    rng = np.random.default_rng(5)
+    eps_r = 1.0 + rng.random(w.N)
+    kappa = w.dt / (w.eps0 * eps_r)
+    gamma = step.hv_gamma(w.hv_c, w.alpha, w.h)
+    keep = step.pec_keep(w.flags, 3)
+    E = rng.standard_normal((w.N, 3)) * keep
+    H = rng.standard_normal((w.N, 3))
+    cop = cstep.Operator(oh)
+    Hn = step.h_update(E, H, oh, w.dt / w.mu0, gamma)
+    Hc = cstep.h_update(E, H, cop, w.dt / w.mu0, gamma)
+    assert np.abs(Hn - Hc).max() <= 1e-13 * np.abs(Hn).max()
+    En = step.e_update(E, Hn, oh, kappa, gamma, keep)
+    Ec = cstep.e_update(E, Hn, cop, kappa, gamma, keep)
+    assert np.abs(En - Ec).max() <= 1e-13 * np.abs(En).max()
+    # a 100-step run of the TM_111 mode with energy samples
+    En_, Hn_, en, _ = step.run(w.E0, w.H0, oh, oh, w.dt, 100, gamma, w.dt / w.eps0, keep, mu0=w.mu0, eps0=w.eps0,
+                               h_e=w.h, h_h=w.h, energy_every=25)
+    Ec_, Hc_, ec = cstep.run(w.E0, w.H0, cop, w.dt, 100, gamma, w.dt / w.eps0, keep, mu0=w.mu0, eps0=w.eps0,
+                             h=w.h, energy_every=25)
+    assert step.rel_l2(Ec_, En_) < 1e-13 and step.rel_l2(Hc_, Hn_) < 1e-13
+    assert np.abs(ec - en).max() <= 1e-13 * en.max()
 
 
 def _knn_cases():
