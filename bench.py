@@ -558,7 +558,7 @@ def main():
             wc = configs.tm_cavity_2d(mode=mode)
             sc, _ = setup_w(wc, "f64")
             stc = sc.state(wc.E0, wc.H0)
-            if not args.no_tune and mode == "FD":
+            if not args.no_tune:
                 sc.autotune(stc, reps=20)
                 stc = sc.state(wc.E0, wc.H0)
             sc.run(stc, 20, use_graph=True)

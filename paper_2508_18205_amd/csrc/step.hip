@@ -349,6 +349,125 @@ __global__ __launch_bounds__(512) void k_e2x(SA<TS, TW> a) {
     }
 }
 
+// ---- 2D, two node sets, small node sets ---------------------------------------
+// As k_h2x / k_e2x with one 64-node tile per workgroup: its four wavefronts
+// each sum every fourth curl chunk and every fourth hyperviscosity chunk, and
+// the partial sums meet in LDS in a fixed order (the small-set scheme of
+// k_h2s / k_e2s below, for the staggered variant).
+template <typename TS, typename TW>
+__global__ __launch_bounds__(256) void k_h2xs(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    __shared__ TC part[3][4][RBFFD_TILE];
+    const int64_t tile = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    const TC e0 = S::ld1(a.E, a.pref[ic]);
+    TC hx0, hy0;
+    S::ld2(a.H, ic, hx0, hy0);
+    TC dx = 0, dy = 0, vx = 0, vy = 0;
+    const int4* pi = a.idx + tile * a.C4 * RBFFD_TILE + lane;
+    const int4* pj = a.idx_h + tile * a.V4 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + tile * a.C4 * 2 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    for (int q = r; q < a.C4; q += 4) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4];
+        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const TC de = S::ld1(a.E, idx4(j, u)) - e0;
+            dx += (TC)wx[u] * de;
+            dy += (TC)wy[u] * de;
+        }
+    }
+    for (int q = r; q < a.V4; q += 4) {
+        const int4 j = pj[q * RBFFD_TILE];
+        TW wh[4];
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC hx, hy;
+            S::ld2(a.H, idx4(j, u), hx, hy);
+            vx += (TC)wh[u] * (hx - hx0);
+            vy += (TC)wh[u] * (hy - hy0);
+        }
+    }
+    if (r > 0) {
+        part[r - 1][0][lane] = dx;
+        part[r - 1][1][lane] = dy;
+        part[r - 1][2][lane] = vx;
+        part[r - 1][3][lane] = vy;
+    }
+    __syncthreads();
+    if (r > 0 || i >= a.N) return;
+    dx = ((dx + part[0][0][lane]) + part[1][0][lane]) + part[2][0][lane];
+    dy = ((dy + part[0][1][lane]) + part[1][1][lane]) + part[2][1][lane];
+    vx = ((vx + part[0][2][lane]) + part[1][2][lane]) + part[2][2][lane];
+    vy = ((vy + part[0][3][lane]) + part[1][3][lane]) + part[2][3][lane];
+    const TC G = (TC)a.g;
+    if (!a.te) {
+        const TC A = (TC)a.a;
+        S::st2(a.out, i, hx0 + A * (-dy + G * vx), hy0 + A * (dx + G * vy));
+    } else {
+        const TC A = -kappa_of(a, i);
+        TC ex = hx0 + A * (-dy + G * vx), ey = hy0 + A * (dx + G * vy);
+        te_wall(a.emask[i], a.wnrm, i, ex, ey);
+        S::st2(a.out, i, ex, ey);
+    }
+}
+
+template <typename TS, typename TW>
+__global__ __launch_bounds__(256) void k_e2xs(SA<TS, TW> a) {
+    using S = Store<TS>;
+    using TC = typename S::C;
+    __shared__ TC part[3][2][RBFFD_TILE];
+    const int64_t tile = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = tile * RBFFD_TILE + lane;
+    const int64_t ic = i < a.N ? i : a.N - 1;
+    const TC e0 = S::ld1(a.E, ic);
+    TC hx0, hy0;
+    S::ld2(a.H, a.pref[ic], hx0, hy0);
+    TC cu = 0, ve = 0;
+    const int4* pi = a.idx + tile * a.C4 * RBFFD_TILE + lane;
+    const int4* pj = a.idx_h + tile * a.V4 * RBFFD_TILE + lane;
+    const TW* pc = a.wc + tile * a.C4 * 2 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    const TW* ph = a.wh + tile * a.V4 * RBFFD_TILE * 4 + lane * WChunk<TW>::LS;
+    for (int q = r; q < a.C4; q += 4) {
+        const int4 j = pi[q * RBFFD_TILE];
+        TW wx[4], wy[4];
+        ldw4p(pc + (q * 2 + 0) * RBFFD_TILE * 4, wx);
+        ldw4p(pc + (q * 2 + 1) * RBFFD_TILE * 4, wy);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            TC hx, hy;
+            S::ld2(a.H, idx4(j, u), hx, hy);
+            cu += (TC)wx[u] * (hy - hy0) - (TC)wy[u] * (hx - hx0);
+        }
+    }
+    for (int q = r; q < a.V4; q += 4) {
+        const int4 j = pj[q * RBFFD_TILE];
+        TW wh[4];
+        ldw4p(ph + q * RBFFD_TILE * 4, wh);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ve += (TC)wh[u] * (S::ld1(a.E, idx4(j, u)) - e0);
+    }
+    if (r > 0) {
+        part[r - 1][0][lane] = cu;
+        part[r - 1][1][lane] = ve;
+    }
+    __syncthreads();
+    if (r > 0 || i >= a.N) return;
+    cu = ((cu + part[0][0][lane]) + part[1][0][lane]) + part[2][0][lane];
+    ve = ((ve + part[0][1][lane]) + part[1][1][lane]) + part[2][1][lane];
+    const TC k = kappa_of(a, i);
+    const TC v = (a.nomask || (a.emask[i] & 1)) ? e0 + k * (cu + (TC)a.g * ve) : (TC)0;
+    S::st1(a.out, i, v);
+}
+
 // ---- 2D, collocated, small node sets ----------------------------------------
 // One 64-node tile per workgroup; its four wavefronts each sum every fourth
 // slot chunk of the tile's nodes (every load is still one contiguous run per
@@ -1475,6 +1594,12 @@ void launch_half(const rbffd_plan* p, bool hupd, const void* E, const void* H, v
         return;
     }
     if constexpr (!kW22) {
+        if (p->dim == 2 && p->var.lds == 3) {
+            const dim3 g1((unsigned)o.tiles), b1(256);
+            if (hupd) hipLaunchKernelGGL((k_h2xs<TS, TW>), g1, b1, 0, st, a);
+            else hipLaunchKernelGGL((k_e2xs<TS, TW>), g1, b1, 0, st, a);
+            return;
+        }
         if (p->dim == 2) {
             if (hupd) hipLaunchKernelGGL((k_h2x<TS, TW>), grid, block, 0, st, a);
             else hipLaunchKernelGGL((k_e2x<TS, TW>), grid, block, 0, st, a);
@@ -1803,8 +1928,8 @@ extern "C" int rbffd_autotune(rbffd_plan* p, rbffd_fields* f, int32_t reps, void
             if (p->dim == 3 && p->opH.stage == 1) cand.push_back(Variant{256, 1, 8, 2});
         }
     }
-    if (p->K == 1 && p->dim == 2 && p->collocated) {
-        // four wavefronts per 64-node tile (small node sets)
+    if (p->K == 1 && p->dim == 2) {
+        // four wavefronts per 64-node tile (small node sets), collocated or two sets
         for (int x : {0, 1}) cand.push_back(Variant{256, x, 8, 3});
     }
     Variant best = p->var;

@@ -214,13 +214,17 @@ def test_two_set_variant_f64():
     got[ph] = pe[st]
     assert (got == oh["curl_idx"]).all()
     _inject(s, oh, oe)
-    stt = s.state(w.E0, w.H0)
-    s.step(stt, w.steps)
     Eo, Ho, _, _ = osetup.run_workload(w, oh, oe)
-    eE = ostep.rel_l2(s.E_original(stt), Eo)
-    eH = ostep.rel_l2(s.H_original(stt), Ho)
-    _announce(f"  rel L2 E {eE:.2e} H {eH:.2e}")
-    assert eE < 1e-12 and eH < 1e-12
+    # the global-gather kernels, and the small-set ones (four wavefronts per
+    # 64-node tile, partial sums meeting in LDS: the same terms in another order)
+    for lds in (0, 3):
+        s.set_variant(block=256, xcd=1, lds=lds)
+        stt = s.state(w.E0, w.H0)
+        s.step(stt, w.steps)
+        eE = ostep.rel_l2(s.E_original(stt), Eo)
+        eH = ostep.rel_l2(s.H_original(stt), Ho)
+        _announce(f"  lds={lds}: rel L2 E {eE:.2e} H {eH:.2e}")
+        assert eE < 1e-12 and eH < 1e-12
 
 
 def test_run_energy_sources_receivers_graph():
