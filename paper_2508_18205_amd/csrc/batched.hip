@@ -171,6 +171,13 @@ __device__ __forceinline__ f4 ldf4(const float* p) {
     const float4 v = *reinterpret_cast<const float4*>(p);
     return {v.x, v.y, v.z, v.w};
 }
+// the halo rows are streamed once per item: non-temporal loads keep them from
+// displacing the tile's weights, which the tile's other slices read from L2
+typedef float ntf4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4 ldf4nt(const float* p) {
+    const ntf4_t v = __builtin_nontemporal_load(reinterpret_cast<const ntf4_t*>(p));
+    return {v.x, v.y, v.z, v.w};
+}
 __device__ __forceinline__ void stf4(float* p, const f4& v) {
     *reinterpret_cast<float4*>(p) = make_float4(v.x, v.y, v.z, v.w);
 }
@@ -220,9 +227,9 @@ __device__ __forceinline__ void stage_slice(const BLA& a, float* sm, int64_t til
         for (int b = 0; b < NB; ++b) {
             if (j[b] < 0) continue;
             const uint64_t r = (uint32_t)j[b];
-            v[b][0] = ldf4(E + r * K);
-            v[b][1] = ldf4(H + 2 * r * K);
-            v[b][2] = ldf4(H + (2 * r + 1) * K);
+            v[b][0] = ldf4nt(E + r * K);
+            v[b][1] = ldf4nt(H + 2 * r * K);
+            v[b][2] = ldf4nt(H + (2 * r + 1) * K);
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
