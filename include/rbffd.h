@@ -370,9 +370,10 @@ int rbffd_autotune(rbffd_plan* plan, rbffd_fields* f, int32_t reps, void* stream
  * gathers with four wavefronts per 64-node tile, each summing a quarter of the
  * stencil (for node sets too small to fill the chip), persist = resident
  * workgroups per CU of the K-field batch's global kernels and the field-slice
- * width of its staged ones: 16 fields for persist >= 16, 4 below 8, else 8,
- * each where K and the LDS allow).  rbffd_set_variant sets it (block a
- * multiple of 64, <= 512, lds 0..3). */
+ * width of its staged ones: 16 fields for persist >= 16 where two
+ * workgroups' slices fit one CU's LDS, 4 below 8, else 8, each where K and
+ * the LDS allow; batch plans start at persist = 16).  rbffd_set_variant sets
+ * it (block a multiple of 64, <= 512, lds 0..3). */
 int rbffd_get_variant(const rbffd_plan* plan, int32_t* out_variant);
 int rbffd_set_variant(rbffd_plan* plan, int32_t block, int32_t xcd, int32_t lds, int32_t persist);
 

@@ -227,9 +227,17 @@ __device__ __forceinline__ void stage_slice(const BLA& a, float* sm, int64_t til
         for (int b = 0; b < NB; ++b) {
             if (j[b] < 0) continue;
             const uint64_t r = (uint32_t)j[b];
-            v[b][0] = ldf4nt(E + r * K);
-            v[b][1] = ldf4nt(H + 2 * r * K);
-            v[b][2] = ldf4nt(H + (2 * r + 1) * K);
+            if constexpr (KSL == 16) {
+                v[b][0] = ldf4nt(E + r * K);
+                v[b][1] = ldf4nt(H + 2 * r * K);
+                v[b][2] = ldf4nt(H + (2 * r + 1) * K);
+            } else {
+                // narrower slices share 64-byte segments with the next
+                // slice's pieces, which find them in L2
+                v[b][0] = ldf4(E + r * K);
+                v[b][1] = ldf4(H + 2 * r * K);
+                v[b][2] = ldf4(H + (2 * r + 1) * K);
+            }
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -639,16 +647,20 @@ BA make_args(const rbffd_plan* p) {
     return a;
 }
 
-// slice width: 16 fields (4 threads per node) when the tile's halo slice fits
-// the LDS budget and the variant asks for it (persist >= 16), 4 fields (one
-// thread per node, the smallest LDS footprint: more resident workgroups) for
-// persist < 8, else 8 (2 threads per node).  The persistent kernels (lds = 2)
-// hold two slices per workgroup.
+// slice width: 16 fields (4 threads per node) when the variant asks for it
+// (persist >= 16) and two workgroups' halo slices fit one CU's LDS (with one
+// workgroup per CU the 8-field slices are faster), 4 fields (one thread per
+// node, the smallest LDS footprint: more resident workgroups) for persist < 8,
+// else 8 (2 threads per node).  The persistent kernels (lds = 2) hold two
+// slices per workgroup.
 int slice_tpn(const rbffd_plan* p) {
     if (!p->var.lds || p->opH.hmax <= 0) return 0;
     const bool pers = p->var.lds == 2;
-    const int64_t cap = pers ? RBFFD_LDS_CU : RBFFD_LDS_BUDGET_BATCH;
-    auto fits = [&](int ksl) { return (pers ? 2 : 1) * p->opH.hmax * 3 * ksl * 4 <= cap; };
+    const int64_t row = (int64_t)p->opH.hmax * 3 * 4;   // LDS bytes per field of a halo slice
+    auto fits = [&](int ksl) {
+        if (pers || ksl == 16) return 2 * row * ksl <= RBFFD_LDS_CU;
+        return row * ksl <= RBFFD_LDS_BUDGET_BATCH;
+    };
     if (p->var.persist >= 16 && p->K % 16 == 0 && fits(16)) return 4;
     if (p->var.persist < 8 && p->K % 4 == 0 && fits(4)) return 1;
     if (p->K % 8 == 0 && fits(8)) return 2;

@@ -212,6 +212,9 @@ extern "C" int rbffd_plan_create(const rbffd_params* prm, int64_t N, const doubl
     p->dim = q.dim;
     p->collocated = q.mode != RBFFD_MODE_STAG2;
     p->K = q.K;
+    // K-field batches start on the staged kernels with 16-field slices where
+    // K and the LDS allow (the tuner's usual choice), else 8 or 4
+    if (q.K > 1) p->var.persist = 16;
     p->n = q.n;
     p->M = (int)n_monomials(q.dim, q.m);
     if (p->M > RBFFD_MAX_MONO) return fail(RBFFD_ESIZE, "too many monomials for the curl system");
