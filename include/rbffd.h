@@ -219,7 +219,9 @@ typedef struct rbffd_adjoint_args {
  * xyz_host [N][dim] doubles, flags_host [N] bytes (bit 2k / 2k+1 = node on
  * the low / high wall normal to axis k; ignored for periodic boxes).  For
  * RBFFD_MODE_STAG2 pass the H set in N_h / xyzH_host / flagsH_host, else 0
- * and NULL.  On success *out owns a new plan (free with rbffd_plan_destroy). */
+ * and NULL.  Periodic boxes: every node of both sets must lie in [lo, hi)
+ * (RBFFD_EINVAL otherwise).  On success *out owns a new plan (free with
+ * rbffd_plan_destroy). */
 int rbffd_plan_create(const rbffd_params* p, int64_t N, const double* xyz_host,
                       const uint8_t* flags_host, int64_t N_h, const double* xyzH_host,
                       const uint8_t* flagsH_host, rbffd_plan** out);

@@ -271,6 +271,13 @@ extern "C" int rbffd_plan_create(const rbffd_params* prm, int64_t N, const doubl
         p->H.xyz_host.assign(xyzH_host, xyzH_host + N_h * q.dim);
         p->H.flags_host.assign(N_h, 0);
         if (flagsH_host && q.bc == RBFFD_BC_PEC) std::memcpy(p->H.flags_host.data(), flagsH_host, N_h);
+        if (q.bc == RBFFD_BC_PERIODIC) {
+            for (int64_t i = 0; i < N_h; ++i)
+                for (int k = 0; k < q.dim; ++k) {
+                    const double x = xyzH_host[i * q.dim + k];
+                    if (!(x >= q.lo[k] && x < q.hi[k])) return fail(RBFFD_EINVAL, "periodic H node outside [lo, hi)");
+                }
+        }
         if (p->n > N_h || p->n > N || p->nh > N || p->nh > N_h) return fail(RBFFD_EINVAL, "stencil larger than a node set");
     } else {
         p->H.N = N;

@@ -106,7 +106,7 @@ struct KnnArgs {
     int d, k, L, bits;
     double lo[3];
     double scale, side;
-    double period[3];       // > 0: periodic axis length (brute-force mode)
+    double period[3];       // periodic: axis lengths (domain [lo, lo + period))
     int periodic;
     int32_t* out;           // [rows][k] original source ids
 };
@@ -184,6 +184,72 @@ struct TopK {
     }
 };
 
+// Periodic image of source x seen from centre c: per axis -1, 0 or +1 as the
+// wrapped difference of sq_dist takes L off, keeps, or adds L to x - c, packed
+// base 3 (0 = no wrap).  Each source belongs to exactly one image of c.
+__device__ __forceinline__ int wrap_code(const double* c, const double* x, int d, const double* per) {
+    int code = 0, w = 1;
+    for (int k = 0; k < d; ++k, w *= 3) {
+        const double dk = x[k] - c[k];
+        code += w * (dk > 0.5 * per[k] ? 2 : (dk < -0.5 * per[k] ? 1 : 0));
+    }
+    return code;
+}
+
+// Ring search of the cell grid around position q, cells in rings of growing
+// Chebyshev radius, until every unscanned cell lies farther than the current
+// k-th nearest.  Distances are taken from the centre c (periodic: wrapped);
+// periodic searches keep only the sources of image `img` (q is that image of
+// c, so the wrapped distance of such a source is its distance from q and the
+// cell bounds hold for it).  Nodes outside the grid box sit in its edge cells,
+// which only makes them farther than the bounds say.
+template <int KMAX>
+__device__ void ring_search(const KnnArgs& a, const double* c, const double* q, int img, TopK<KMAX>& tk) {
+    const int G = 1 << a.L;
+    const double cs = a.side / G;
+    int cc[3] = {0, 0, 0};
+    for (int k = 0; k < a.d; ++k) cc[k] = (int)(quantise(q[k], a.lo[k], a.scale, a.bits) >> (a.bits - a.L));
+    for (int r = 0;; ++r) {
+        const int z0 = a.d == 3 ? -r : 0, z1 = a.d == 3 ? r : 0;
+        for (int dz = z0; dz <= z1; ++dz)
+            for (int dy = -r; dy <= r; ++dy)
+                for (int dx = -r; dx <= r; ++dx) {
+                    const int m = max(abs(dx), max(abs(dy), abs(dz)));
+                    if (m != r) continue;
+                    const int x = cc[0] + dx, y = cc[1] + dy, z = cc[2] + dz;
+                    if (x < 0 || x >= G || y < 0 || y >= G || (a.d == 3 && (z < 0 || z >= G))) continue;
+                    uint64_t qc[3] = {(uint64_t)x, (uint64_t)y, (uint64_t)z};
+                    const uint64_t cid = interleave(qc, a.d, a.L);
+                    const int32_t e = a.cend[cid];
+                    for (int32_t j = a.cstart[cid]; j < e; ++j) {
+                        const double* xs = a.sxyz + (int64_t)j * a.d;
+                        if (a.periodic && wrap_code(c, xs, a.d, a.period) != img) continue;
+                        tk.push(sq_dist(c, xs, a.d, a.period, a.periodic), a.sorig[j], a.k);
+                    }
+                }
+        // every node outside the scanned box is at least R away
+        bool whole = true;
+        double R = 1e300;
+        for (int k = 0; k < a.d; ++k) {
+            if (cc[k] - r > 0) {
+                whole = false;
+                R = fmin(R, q[k] - (a.lo[k] + (cc[k] - r) * cs));
+            }
+            if (cc[k] + r < G - 1) {
+                whole = false;
+                R = fmin(R, (a.lo[k] + (cc[k] + r + 1) * cs) - q[k]);
+            }
+        }
+        if (whole) break;
+        R -= 1e-9 * cs;
+        if (tk.cnt >= a.k && R > 0.0 && tk.worst() < R * R) break;
+    }
+}
+
+// Periodic sets search the images c + s P (s in {-1, 0, 1}^d) of each centre,
+// c itself first; an image farther from the domain box [lo, hi) (which holds
+// every node of a periodic set) than the current k-th nearest holds none of
+// the k nearest and is skipped.
 template <int KMAX>
 __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -191,44 +257,22 @@ __global__ __launch_bounds__(64) void k_knn(KnnArgs a) {
     double c[3] = {0, 0, 0};
     for (int k = 0; k < a.d; ++k) c[k] = a.cxyz[t * a.d + k];
     TopK<KMAX> tk;
+    ring_search(a, c, c, 0, tk);
     if (a.periodic) {
-        for (int64_t j = 0; j < a.Ns; ++j) tk.push(sq_dist(c, a.sxyz + j * a.d, a.d, a.period, 1), a.sorig[j], a.k);
-    } else {
-        const int G = 1 << a.L;
-        const double cs = a.side / G;
-        int cc[3] = {0, 0, 0};
-        for (int k = 0; k < a.d; ++k) cc[k] = (int)(quantise(c[k], a.lo[k], a.scale, a.bits) >> (a.bits - a.L));
-        for (int r = 0;; ++r) {
-            const int z0 = a.d == 3 ? -r : 0, z1 = a.d == 3 ? r : 0;
-            for (int dz = z0; dz <= z1; ++dz)
-                for (int dy = -r; dy <= r; ++dy)
-                    for (int dx = -r; dx <= r; ++dx) {
-                        const int m = max(abs(dx), max(abs(dy), abs(dz)));
-                        if (m != r) continue;
-                        const int x = cc[0] + dx, y = cc[1] + dy, z = cc[2] + dz;
-                        if (x < 0 || x >= G || y < 0 || y >= G || (a.d == 3 && (z < 0 || z >= G))) continue;
-                        uint64_t q[3] = {(uint64_t)x, (uint64_t)y, (uint64_t)z};
-                        const uint64_t cid = interleave(q, a.d, a.L);
-                        const int32_t e = a.cend[cid];
-                        for (int32_t j = a.cstart[cid]; j < e; ++j)
-                            tk.push(sq_dist(c, a.sxyz + (int64_t)j * a.d, a.d, a.period, 0), a.sorig[j], a.k);
-                    }
-            // every node outside the scanned box is at least R away
-            bool whole = true;
-            double R = 1e300;
-            for (int k = 0; k < a.d; ++k) {
-                if (cc[k] - r > 0) {
-                    whole = false;
-                    R = fmin(R, c[k] - (a.lo[k] + (cc[k] - r) * cs));
-                }
-                if (cc[k] + r < G - 1) {
-                    whole = false;
-                    R = fmin(R, (a.lo[k] + (cc[k] + r + 1) * cs) - c[k]);
-                }
+        const int nimg = a.d == 3 ? 27 : 9;
+        for (int img = 1; img < nimg; ++img) {
+            double q[3] = {c[0], c[1], c[2]};
+            double b2 = 0.0;
+            for (int k = 0, v = img; k < a.d; ++k, v /= 3) {
+                const int s = v % 3;   // 1: image c - L, 2: image c + L
+                if (s == 1) q[k] = c[k] - a.period[k];
+                if (s == 2) q[k] = c[k] + a.period[k];
+                const double lo = a.lo[k], hi = a.lo[k] + a.period[k];
+                const double g = q[k] < lo ? lo - q[k] : (q[k] > hi ? q[k] - hi : 0.0);
+                b2 += g * g;
             }
-            if (whole) break;
-            R -= 1e-9 * cs;
-            if (tk.cnt >= a.k && R > 0.0 && tk.worst() < R * R) break;
+            if (tk.cnt >= a.k && b2 * (1.0 - 1e-12) > tk.worst()) continue;
+            ring_search(a, c, q, img, tk);
         }
     }
     tk.finish();
@@ -1116,7 +1160,7 @@ void take_search(WS& w, Search& s, int64_t N, int d, int width, bool periodic) {
     s.vals_in = w.take<int32_t>(N);
     s.sperm = w.take<int32_t>(N);
     s.sxyz = w.take<double>(N * d);
-    s.L = periodic ? 1 : cell_level(N, d, width);
+    s.L = cell_level(N, d, width);
     s.ncells = (int64_t)1 << (d * s.L);
     s.cstart = w.take<int32_t>(s.ncells);
     s.cend = w.take<int32_t>(s.ncells);

@@ -78,6 +78,28 @@ def test_order_and_stencils_bit_exact(case):
     assert (st == ref).all()
 
 
+@pytest.mark.parametrize("case", ["2d_200k", "3d_54k"])
+def test_periodic_knn_of_large_anisotropic_boxes(case):
+    # the periodic cell search (each centre and, where they can hold one of
+    # its k nearest, its images one period away) against the oracle's cell
+    # search, on boxes whose sides (periods) differ
+    _announce(f"periodic kNN {case}")
+    if case == "2d_200k":
+        lo, hi = (0.0, 0.0), (4.0, 1.25)
+        xyz, flags, h = nodes.jittered_grid((800, 250), lo=lo, hi=hi, periodic=True, seed=21)
+        w = configs.Workload("p2", 2, xyz, flags, h, 12, 2, 2, 31, 1e-3, 1, bc="PERIODIC", lo=lo, hi=hi)
+    else:
+        lo, hi = (0.0, 0.0, 0.0), (2.0, 1.0, 1.0)
+        xyz, flags, h = nodes.jittered_grid((60, 30, 30), lo=lo, hi=hi, periodic=True, seed=22)
+        w = configs.Workload("p3", 3, xyz, flags, h, 35, 2, 2, configs._hv_default(3, 2), 1e-3, 1,
+                             bc="PERIODIC", lo=lo, hi=hi)
+    s = Solver.from_workload(w, precision="f64")
+    st = _orig_stencils(s, s.stencils())
+    ref = knn.knn_cells(w.xyz, max(w.n, w.n_hv), period=w.period)
+    _announce(f"  {w.N} nodes, k = {st.shape[1]}: {(st != ref).any(axis=1).sum()} rows differ")
+    assert (st == ref).all()
+
+
 def test_weights_of_systems_beyond_the_register_solver():
     # a curl stencil of n = 100 with m = 4 (115 unknowns + 2 right-hand sides)
     # exceeds the register-resident solver and takes the LDS-resident one;
