@@ -94,7 +94,7 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int cb, int K, bool adjo
         o.pidx = b.take_bytes(T * o.S4 * 16);
         // halo lists of 256-node workgroup tiles (single field and K-field batch)
         o.Q8 = (int)cdiv(o.ns - 1, 8);
-        o.wgt = K > 1 ? RBFFD_WGT_BATCH : RBFFD_WGT;
+        o.wgt = K > 1 ? RBFFD_WGT_BATCH : (dim == 3 ? RBFFD_WGT_3D : RBFFD_WGT);
         o.nwg = cdiv(o.tiles, o.wgt / RBFFD_TILE);
         o.lidx = b.take<uint16_t>(T * o.Q8 * 8);
         if (K > 1) o.lself = b.take<uint16_t>(T);

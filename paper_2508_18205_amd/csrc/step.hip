@@ -1034,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
 }
 
 template <typename TS, typename TW>
-__global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
+__global__ __launch_bounds__(RBFFD_WGT_3D) void k_h3l(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
     TC* sE = lds_base<TC>();                           // 3 values per entry
@@ -1055,7 +1055,7 @@ __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
             st_lds3(sH + 3 * k, hh);
         });
     __syncthreads();
-    const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
+    const int64_t tile = (int64_t)wg * (RBFFD_WGT_3D / RBFFD_TILE) + (threadIdx.x >> 6);
     if (tile >= a.tiles) return;
     const int lane = threadIdx.x & 63;
     const int64_t i = tile * RBFFD_TILE + lane;
@@ -1112,7 +1112,7 @@ __global__ __launch_bounds__(256) void k_h3l(SA<TS, TW> a) {
 }
 
 template <typename TS, typename TW>
-__global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
+__global__ __launch_bounds__(RBFFD_WGT_3D) void k_e3l(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
     TC* sE = lds_base<TC>();
@@ -1133,7 +1133,7 @@ __global__ __launch_bounds__(256) void k_e3l(SA<TS, TW> a) {
             st_lds3(sH + 3 * k, hh);
         });
     __syncthreads();
-    const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
+    const int64_t tile = (int64_t)wg * (RBFFD_WGT_3D / RBFFD_TILE) + (threadIdx.x >> 6);
     if (tile >= a.tiles) return;
     const int lane = threadIdx.x & 63;
     const int64_t i = tile * RBFFD_TILE + lane;
@@ -1274,13 +1274,13 @@ __device__ __forceinline__ void hv_sums3(const TC* sF, const uint4* pl, const TW
 }
 
 template <typename TS, typename TW>
-__global__ __launch_bounds__(256) void k_h3p(SA<TS, TW> a) {
+__global__ __launch_bounds__(RBFFD_WGT_3D) void k_h3p(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
     TC* sF = lds_base<TC>();
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
-    const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
+    const int64_t tile = (int64_t)wg * (RBFFD_WGT_3D / RBFFD_TILE) + (threadIdx.x >> 6);
     const bool live = tile < a.tiles;
     const int64_t tl = live ? tile : a.tiles - 1;
     const int lane = threadIdx.x & 63;
@@ -1309,13 +1309,13 @@ __global__ __launch_bounds__(256) void k_h3p(SA<TS, TW> a) {
 }
 
 template <typename TS, typename TW>
-__global__ __launch_bounds__(256) void k_e3p(SA<TS, TW> a) {
+__global__ __launch_bounds__(RBFFD_WGT_3D) void k_e3p(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
     TC* sF = lds_base<TC>();
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
-    const int64_t tile = (int64_t)wg * (RBFFD_WGT / RBFFD_TILE) + (threadIdx.x >> 6);
+    const int64_t tile = (int64_t)wg * (RBFFD_WGT_3D / RBFFD_TILE) + (threadIdx.x >> 6);
     const bool live = tile < a.tiles;
     const int64_t tl = live ? tile : a.tiles - 1;
     const int lane = threadIdx.x & 63;
@@ -1559,7 +1559,7 @@ void launch_half(const rbffd_plan* p, bool hupd, const void* E, const void* H, v
     }
     if (p->collocated && o.hmax > 0 && p->var.lds && !(p->var.lds == 3 && p->dim == 2)) {
         using TC = typename Store<TS>::C;
-        const dim3 grid((unsigned)o.nwg), block(RBFFD_WGT);
+        const dim3 grid((unsigned)o.nwg), block(o.wgt);
         if (p->dim == 2) {
             const size_t lds = (size_t)(((o.hmax + 3) & ~3) + 2 * o.hmax) * sizeof(TC);
             if (hupd) hipLaunchKernelGGL((k_h2l<TS, TW>), grid, block, lds, st, a);
