@@ -1029,10 +1029,10 @@ __global__ void k_tweights(const int32_t* tsrc, const int32_t* tslot, int64_t E,
 }
 
 // ---------------------------------------------------------------------------
-// Halo lists for LDS staging: per 256-node workgroup tile the sorted unique
-// source nodes of its stencils, and per (node, slot) the 16-bit position of
-// the slot's node in that list.  Built from one global sort of
-// (tile, source) keys.
+// Halo lists for LDS staging: per workgroup tile (256 nodes in 2D, 512 in 3D,
+// 128 in K-field batch plans) the sorted unique source nodes of its
+// stencils, and per (node, slot) the 16-bit position of the slot's node in
+// that list.  Built from one global sort of (tile, source) keys.
 // ---------------------------------------------------------------------------
 __global__ void k_hkeys(const int32_t* st, int64_t N, int ns, int tsz, uint64_t* keys) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

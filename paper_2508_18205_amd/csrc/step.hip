@@ -752,7 +752,8 @@ __global__ __launch_bounds__(512) void k_e3(SA<TS, TW> a) {
 }
 
 // ---- LDS-staged variants ------------------------------------------------------
-// A workgroup owns 256 consecutive nodes (4 wavefront tiles).  It first copies
+// A workgroup owns 256 consecutive nodes in 2D, 512 in 3D (4 or 8 wavefront
+// tiles).  It first copies
 // the field values of every node its stencils touch (the sorted halo list)
 // into LDS with one coalesced pass, then each node sums over its slots with
 // 16-bit halo positions (8 per 16-byte load) instead of 32-bit global indices
