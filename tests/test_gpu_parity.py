@@ -223,6 +223,49 @@ def test_cube_3d_f64_and_f32():
         assert eE < tol and eH < tol
 
 
+def _periodic_box_3d():
+    # periodic 3D box with sides (periods) 1.25, 1 and 0.75 (10 x 8 x 6
+    # jittered nodes), smooth periodic E and H, 60 steps
+    lo, hi = (0.0, 0.0, 0.0), (1.25, 1.0, 0.75)
+    xyz, flags, h = nodes.jittered_grid((10, 8, 6), lo=lo, hi=hi, periodic=True, seed=31)
+    w = configs.Workload("periodic_box_3d", 3, xyz, flags, h, 35, 2, 2, configs._hv_default(3, 2), 1e-3, 60,
+                         bc="PERIODIC", lo=lo, hi=hi)
+    ph = 2.0 * np.pi * (xyz - np.asarray(lo)) / (np.asarray(hi) - np.asarray(lo))
+    w.E0 = np.stack([np.sin(ph[:, 1]) * np.cos(ph[:, 2]), np.sin(ph[:, 2] + ph[:, 0]),
+                     np.cos(ph[:, 0]) * np.sin(ph[:, 1])], axis=1)
+    w.H0 = 0.5 * np.stack([np.cos(ph[:, 2]), np.sin(ph[:, 0]) * np.sin(ph[:, 2]), np.cos(ph[:, 1] - ph[:, 0])],
+                          axis=1)
+    return w
+
+
+def test_periodic_3d_box_vs_oracle():
+    # the GPU's own stencils (periodic images) and weights (minimum-image
+    # offsets) against the oracle's, then the fields end to end (FP64 bar
+    # 1e-9) and with the oracle's weights injected (FP64 1e-12, FP32 1e-5)
+    _announce("periodic 3D box vs oracle")
+    w = _periodic_box_3d()
+    oh, _ = osetup.operators(w)
+    Eo, Ho, _, _ = osetup.run_workload(w, oh, oh)
+    s = Solver.from_workload(w, precision="f64")
+    assert (_orig_stencils(s, s.stencils()) == oh["stencil"]).all()
+    ec = _weight_err(s.weights(_abi.OP_CURL_H), oh["curl_w"][s.perm])
+    eh = _weight_err(s.weights(_abi.OP_HV_H), oh["hv_w"][s.perm])
+    st = s.state(w.E0, w.H0)
+    s.step(st, w.steps)
+    eE, eH = ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho)
+    _announce(f"  weights curl {ec.max():.2e} hv {eh.max():.2e}; own weights E {eE:.2e} H {eH:.2e}")
+    assert ec.max() < 1e-9 and eh.max() < 1e-9
+    assert eE < 1e-9 and eH < 1e-9
+    for prec, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        s = Solver.from_workload(w, precision=prec)
+        _inject(s, oh)
+        st = s.state(w.E0, w.H0)
+        s.step(st, w.steps)
+        eE, eH = ostep.rel_l2(s.E_original(st), Eo), ostep.rel_l2(s.H_original(st), Ho)
+        _announce(f"  {prec}, oracle weights: E {eE:.2e} H {eH:.2e}")
+        assert eE < tol and eH < tol
+
+
 def test_two_set_variant_f64():
     _announce("two-set variant f64")
     w = configs.tm_cavity_2d(n_side=31, mode="STAG2", chat=1e-3, steps=300)
