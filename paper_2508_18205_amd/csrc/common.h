@@ -16,10 +16,11 @@
 #define RBFFD_WGT 256             // nodes per LDS-staged workgroup tile (4 wavefronts)
 #define RBFFD_WGT_BATCH 128       // K-field batch: nodes per staged tile (two workgroups share a CU)
 #define RBFFD_WGT_3D 512          // 3D: nodes per staged workgroup tile (8 wavefronts)
+#define RBFFD_WGT_3D_F32 1024     // 3D with FP32 fields (16 wavefronts)
 #define RBFFD_LDS_BUDGET 65536    // bytes of LDS one staged workgroup may use
-#define RBFFD_LDS_BUDGET_3D 131072 // 3D: both operands together up to this size (FP64: one
-                                   // 512-node workgroup per CU; the tuner also tries one
-                                   // operand at a time, two per CU)
+#define RBFFD_LDS_BUDGET_3D 131072 // 3D: both operands together up to this size (one
+                                   // workgroup per CU; the tuner also tries one operand
+                                   // at a time, two per CU)
 #define RBFFD_KSLICE 16           // widest field slice of the staged K-field batch
 #define RBFFD_LDS_BUDGET_BATCH 122880
 #define RBFFD_LDS_CU 163840       // LDS of one CU (gfx950)

@@ -92,10 +92,11 @@ void layout_block(Bump& b, OpBlock& o, int dim, int wb, int cb, int K, bool adjo
     if (!o.cross) {
         o.st_union = b.take<int32_t>(o.Nt * o.ns);
         o.pidx = b.take_bytes(T * o.S4 * 16);
-        // halo lists per workgroup tile: 256 nodes in 2D, 512 in 3D, 128 in
-        // K-field batch plans
+        // halo lists per workgroup tile: 256 nodes in 2D, in 3D 1024 with
+        // FP32 weights (16-byte chunks) and 512 with FP64, 128 in K-field
+        // batch plans
         o.Q8 = (int)cdiv(o.ns - 1, 8);
-        o.wgt = K > 1 ? RBFFD_WGT_BATCH : (dim == 3 ? RBFFD_WGT_3D : RBFFD_WGT);
+        o.wgt = K > 1 ? RBFFD_WGT_BATCH : (dim == 3 ? (cb == 16 ? RBFFD_WGT_3D_F32 : RBFFD_WGT_3D) : RBFFD_WGT);
         o.nwg = cdiv(o.tiles, o.wgt / RBFFD_TILE);
         o.lidx = b.take<uint16_t>(T * o.Q8 * 8);
         if (K > 1) o.lself = b.take<uint16_t>(T);

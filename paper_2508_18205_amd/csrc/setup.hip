@@ -1029,8 +1029,9 @@ __global__ void k_tweights(const int32_t* tsrc, const int32_t* tslot, int64_t E,
 }
 
 // ---------------------------------------------------------------------------
-// Halo lists for LDS staging: per workgroup tile (256 nodes in 2D, 512 in 3D,
-// 128 in K-field batch plans) the sorted unique source nodes of its
+// Halo lists for LDS staging: per workgroup tile (256 nodes in 2D; in 3D 1024
+// with FP32 weights, 512 with FP64; 128 in K-field batch plans) the sorted
+// unique source nodes of its
 // stencils, and per (node, slot) the 16-bit position of the slot's node in
 // that list.  Built from one global sort of (tile, source) keys.
 // ---------------------------------------------------------------------------

@@ -752,8 +752,8 @@ __global__ __launch_bounds__(512) void k_e3(SA<TS, TW> a) {
 }
 
 // ---- LDS-staged variants ------------------------------------------------------
-// A workgroup owns 256 consecutive nodes in 2D, 512 in 3D (4 or 8 wavefront
-// tiles).  It first copies
+// A workgroup owns 256 consecutive nodes in 2D, in 3D 1024 with FP32 weights
+// and 512 with FP64 (4, 16 or 8 wavefront tiles).  It first copies
 // the field values of every node its stencils touch (the sorted halo list)
 // into LDS with one coalesced pass, then each node sums over its slots with
 // 16-bit halo positions (8 per 16-byte load) instead of 32-bit global indices
@@ -1035,7 +1035,7 @@ __global__ __launch_bounds__(256) void k_e2l(SA<TS, TW> a) {
 }
 
 template <typename TS, typename TW>
-__global__ __launch_bounds__(RBFFD_WGT_3D) void k_h3l(SA<TS, TW> a) {
+__global__ __launch_bounds__(RBFFD_WGT_3D_F32) void k_h3l(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
     TC* sE = lds_base<TC>();                           // 3 values per entry
@@ -1056,7 +1056,7 @@ __global__ __launch_bounds__(RBFFD_WGT_3D) void k_h3l(SA<TS, TW> a) {
             st_lds3(sH + 3 * k, hh);
         });
     __syncthreads();
-    const int64_t tile = (int64_t)wg * (RBFFD_WGT_3D / RBFFD_TILE) + (threadIdx.x >> 6);
+    const int64_t tile = (int64_t)wg * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (tile >= a.tiles) return;
     const int lane = threadIdx.x & 63;
     const int64_t i = tile * RBFFD_TILE + lane;
@@ -1113,7 +1113,7 @@ __global__ __launch_bounds__(RBFFD_WGT_3D) void k_h3l(SA<TS, TW> a) {
 }
 
 template <typename TS, typename TW>
-__global__ __launch_bounds__(RBFFD_WGT_3D) void k_e3l(SA<TS, TW> a) {
+__global__ __launch_bounds__(RBFFD_WGT_3D_F32) void k_e3l(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
     TC* sE = lds_base<TC>();
@@ -1134,7 +1134,7 @@ __global__ __launch_bounds__(RBFFD_WGT_3D) void k_e3l(SA<TS, TW> a) {
             st_lds3(sH + 3 * k, hh);
         });
     __syncthreads();
-    const int64_t tile = (int64_t)wg * (RBFFD_WGT_3D / RBFFD_TILE) + (threadIdx.x >> 6);
+    const int64_t tile = (int64_t)wg * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (tile >= a.tiles) return;
     const int lane = threadIdx.x & 63;
     const int64_t i = tile * RBFFD_TILE + lane;
@@ -1275,13 +1275,13 @@ __device__ __forceinline__ void hv_sums3(const TC* sF, const uint4* pl, const TW
 }
 
 template <typename TS, typename TW>
-__global__ __launch_bounds__(RBFFD_WGT_3D) void k_h3p(SA<TS, TW> a) {
+__global__ __launch_bounds__(RBFFD_WGT_3D_F32) void k_h3p(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
     TC* sF = lds_base<TC>();
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
-    const int64_t tile = (int64_t)wg * (RBFFD_WGT_3D / RBFFD_TILE) + (threadIdx.x >> 6);
+    const int64_t tile = (int64_t)wg * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const bool live = tile < a.tiles;
     const int64_t tl = live ? tile : a.tiles - 1;
     const int lane = threadIdx.x & 63;
@@ -1310,13 +1310,13 @@ __global__ __launch_bounds__(RBFFD_WGT_3D) void k_h3p(SA<TS, TW> a) {
 }
 
 template <typename TS, typename TW>
-__global__ __launch_bounds__(RBFFD_WGT_3D) void k_e3p(SA<TS, TW> a) {
+__global__ __launch_bounds__(RBFFD_WGT_3D_F32) void k_e3p(SA<TS, TW> a) {
     using S = Store<TS>;
     using TC = typename S::C;
     TC* sF = lds_base<TC>();
     const int wg = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int h0 = a.hoff[wg], hc = a.hoff[wg + 1] - h0;
-    const int64_t tile = (int64_t)wg * (RBFFD_WGT_3D / RBFFD_TILE) + (threadIdx.x >> 6);
+    const int64_t tile = (int64_t)wg * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const bool live = tile < a.tiles;
     const int64_t tl = live ? tile : a.tiles - 1;
     const int lane = threadIdx.x & 63;
