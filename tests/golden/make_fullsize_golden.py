@@ -16,6 +16,12 @@ tests/test_gpu_fullsize_parity.py and by the benchmark:
   tm111_3d_8M.npz     the 3D cube: 200^3 jittered nodes on the PEC unit cube,
                       n = 35, m = 2, alpha = 2 (n_hv = 71), chat = 1e-3, the
                       TM_111 mode, 2000 steps
+  batch64_250k.npz    the K-field batch workload: 500^2 jittered nodes on the
+                      PEC unit square, n = 25, m = 2, alpha = 2 (n_hv = 31),
+                      chat = 1e-4, 64 seeded Gaussian pulses (sigma = 20 h),
+                      the configured 5000 steps; fields 0, 21, 42 and 63 are
+                      run (each is a single-field run of its pulse) and stored
+                      with a leading field axis
 
 Each file holds: the sampled node ids (original order) and the oracle's E
 [S, 1], H [S, 2] there after the last step; the energy U^n of eq. 20 every
@@ -24,8 +30,8 @@ each full field component on 8 seeded standard normal vectors g_j (numpy
 default_rng(seed 2508) drawn as [8, N]), which turn any widespread
 difference into a global relative L2 estimate; and the run's parameters.
 
-Usage:  python tests/golden/make_fullsize_golden.py [a3] [a2] [c3]
-(about 15, 40 and 75 minutes on 8 cores; c3 needs ~30 GB of memory).
+Usage:  python tests/golden/make_fullsize_golden.py [a3] [a2] [c3] [b4]
+(about 15, 40, 75 and 5 minutes on 8 cores; c3 needs ~30 GB of memory).
 """
 import math
 import os
@@ -126,7 +132,49 @@ def run_cube(procs=8):
         f"[{(en / en[0]).min():.6f}, {(en / en[0]).max():.6f}]")
 
 
+BATCH_FIELDS = (0, 21, 42, 63)
+
+
+def run_batch(procs=8):
+    """Fields of the K = 64 batch workload (batched_2d as the benchmark runs
+    it), each run alone for the configured 5000 steps."""
+    from oracle import setup as osetup
+    t0 = time.time()
+    w = configs.batched_2d(scale=1.0)
+    stencils = knn.knn_cells(w.xyz, max(w.n, w.n_hv))
+    curl_w, hv_w = osetup.weights_parallel(w.xyz, stencils, w.n, w.m, w.n_hv, w.alpha, procs)
+    log(f"[b4] N={w.N} K={w.K}: stencils and weights {time.time() - t0:.0f} s")
+    op = cstep.Operator({"curl_idx": stencils[:, :w.n], "curl_w": curl_w, "hv_idx": stencils[:, :w.n_hv],
+                         "hv_w": hv_w})
+    del curl_w, hv_w
+    gamma = ostep.hv_gamma(w.hv_c, w.alpha, w.h)
+    keep = ostep.pec_keep(w.flags, 2)[:, 0]
+    steps, every = w.steps, 100
+    smp = sample_nodes(w, 34, 2000, 0, 0.0)
+    g = np.random.default_rng(PROJ_SEED).standard_normal((N_PROJ, w.N))
+    Es, Hs, ens, pE, pH = [], [], [], [], []
+    for k in BATCH_FIELDS:
+        t0 = time.time()
+        E, H, en = cstep.run(w.E0_batch[k], np.zeros((w.N, 2)), op, w.dt, steps, gamma, w.dt / w.eps0, keep,
+                             mu0=w.mu0, eps0=w.eps0, h=w.h, energy_every=every)
+        Es.append(E[smp]); Hs.append(H[smp]); ens.append(en)
+        pE.append(projections(E, g)); pH.append(projections(H, g))
+        log(f"[b4] field {k}: {steps} steps in {time.time() - t0:.0f} s; u range "
+            f"[{(en / en[0]).min():.6f}, {(en / en[0]).max():.6f}]")
+    out = os.path.join(HERE, "batch64_250k.npz")
+    np.savez_compressed(out, nodes=smp, fields=np.array(BATCH_FIELDS), E=np.stack(Es), H=np.stack(Hs),
+                        energy=np.stack(ens), energy_every=every, projE=np.stack(pE), projH=np.stack(pH), N=w.N,
+                        K=w.K, steps=steps, alpha=w.alpha, n_hv=w.n_hv, chat=w.chat, n=w.n, m=w.m,
+                        proj_seed=PROJ_SEED, threads=cstep.threads())
+    log(f"[b4] wrote {out}")
+
+
 def main(which):
+    if "b4" in which:
+        run_batch()
+        which = [x for x in which if x != "b4"]
+        if not which:
+            return
     if "c3" in which:
         run_cube()
         which = [x for x in which if x != "c3"]

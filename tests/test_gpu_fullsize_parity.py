@@ -16,6 +16,9 @@ configuration the benchmark times (autotuned variant, HIP-graph replay).
 * The 8.0M-node 3D cube (PEC unit cube, n = 35, m = 2, alpha = 2, TM_111
   mode), 2000 steps end to end in FP64 and FP32 against the oracle's stored
   FP64 run (tests/golden/tm111_3d_8M.npz), the same checks and bars.
+* The K = 64 batch (250k nodes, n = 25, m = 2, alpha = 2), the configured
+  5000 steps end to end, fields 0, 21, 42 and 63 against the oracle's
+  single-field FP64 runs (tests/golden/batch64_250k.npz), FP32 bar.
 * The two-set variant at the 2D cavity's size (51^2 E nodes, 50^2 H nodes,
   TM_11, one period = 1000 steps), FP64 with injected oracle weights
   (1e-12) and end to end (1e-9), against the oracle run in the test.
@@ -132,6 +135,44 @@ def test_cube_8M_end_to_end_vs_oracle(precision):
     assert eE < tol and eH < tol
     assert eU < tol
     assert gE < tol and gH < tol
+
+
+def test_batch_250k_end_to_end_vs_oracle():
+    # the K = 64 batch as the benchmark runs it (250k nodes, tuned variant,
+    # graph replay), the configured 5000 steps end to end; four of its fields
+    # against the oracle's single-field FP64 runs of those pulses
+    path = os.path.join(GOLD, "batch64_250k.npz")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/batch64_250k.npz not written (tests/golden/make_fullsize_golden.py b4)")
+    g = np.load(path)
+    w = configs.batched_2d(scale=1.0)
+    assert int(g["N"]) == w.N and int(g["K"]) == w.K and (w.alpha, w.n_hv, w.n) == (
+        int(g["alpha"]), int(g["n_hv"]), int(g["n"]))
+    steps, every = int(g["steps"]), int(g["energy_every"])
+    _announce(f"batch 250k: N={w.N} K={w.K} steps={steps}")
+    s = Solver.from_workload(w, precision="f32", K=w.K)
+    H0 = np.zeros((w.K, w.N, 2))
+    st = s.state_batched(w.E0_batch, H0)
+    s.autotune(st, reps=3)
+    st = s.state_batched(w.E0_batch, H0)
+    r = s.run(st, steps, energy_every=every, use_graph=True)
+    E = s.to_original(st.E)[:, 0, :]
+    H = s.to_original(st.H)
+    en = np.asarray(r["energy"])
+    nodes = g["nodes"]
+    gv = np.random.default_rng(int(g["proj_seed"])).standard_normal((g["projE"].shape[-1], w.N))
+    worst = 0.0
+    for j, k in enumerate(g["fields"]):
+        eE = _rel(E[nodes, k][:, None], g["E"][j])
+        eH = _rel(H[nodes, :, k], g["H"][j])
+        eU = float(np.abs(en[:, k] / g["energy"][j] - 1.0).max())
+        pE = np.stack([gv @ E[:, k]])
+        pH = np.stack([gv @ H[:, c, k] for c in range(2)])
+        gE, gH = _proj_rel(pE, g["projE"][j]), _proj_rel(pH, g["projH"][j])
+        _announce(f"  field {k}: sampled E {eE:.2e} H {eH:.2e}; energy {eU:.2e}; projections E {gE:.2e} H {gH:.2e}")
+        worst = max(worst, eE, eH, eU, gE, gH)
+    _announce(f"  variant {s.variant()}: worst {worst:.2e}")
+    assert worst < 1e-5
 
 
 def _inject(s, oh, oe):
