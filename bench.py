@@ -175,9 +175,10 @@ def cpu_baseline(w, seconds=15.0):
 
 def golden(tag):
     """The FP64 oracle's stored results of a full-size run (tests/golden):
-    tag a3 / a2 (the 1M-node pulse) or "tm111_3d_8M" (the 3D cube)."""
+    tag a3 / a2 (the 1M-node pulse), "tm111_3d_8M" (the 3D cube) or
+    "batch64_250k" (four fields of the K = 64 batch workload)."""
     import numpy as np
-    name = tag if tag.startswith("tm111") else f"pulse2d_1M_{tag}"
+    name = tag if tag.startswith(("tm111", "batch64")) else f"pulse2d_1M_{tag}"
     path = os.path.join(ROOT, "tests", "golden", f"{name}.npz")
     return np.load(path) if os.path.exists(path) else None
 
@@ -595,6 +596,37 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         tb = e0.elapsed_time(e1) * 1e-3
+        # the configured steps from the initial fields, four fields against
+        # the oracle's single-field runs of their pulses
+        gb = golden("batch64_250k")
+        acc_b = None
+        if gb is not None and int(gb["steps"]) == wb.steps:
+            stb = sb.state_batched(wb.E0_batch, np.zeros((64, wb.N, 2)))
+            rb = sb.run(stb, wb.steps, energy_every=int(gb["energy_every"]), use_graph=True)
+            Eb, Hb = sb.to_original(stb.E)[:, 0, :], sb.to_original(stb.H)
+            enb = np.asarray(rb["energy"])
+            nb = gb["nodes"]
+            gvb = np.random.default_rng(int(gb["proj_seed"])).standard_normal((gb["projE"].shape[-1], wb.N))
+            acc_b = {"steps": wb.steps, "fields": [int(k) for k in gb["fields"]]}
+            worst = dict(sampled_rel_l2_E=0.0, sampled_rel_l2_H=0.0, energy_rel_max=0.0,
+                         whole_field_rel_l2_E_est=0.0, whole_field_rel_l2_H_est=0.0)
+            for j, k in enumerate(gb["fields"]):
+                refE, refH = gb["E"][j], gb["H"][j]
+                pE = gvb @ Eb[:, k]
+                pH = np.stack([gvb @ Hb[:, c, k] for c in range(2)])
+                vals = dict(
+                    sampled_rel_l2_E=float(np.linalg.norm(Eb[nb, k] - refE[:, 0]) / np.linalg.norm(refE[:, 0])),
+                    sampled_rel_l2_H=max(float(np.linalg.norm(Hb[nb, c, k] - refH[:, c]) / np.linalg.norm(refH[:, c]))
+                                         for c in range(2)),
+                    energy_rel_max=float(np.abs(enb[:, k] / gb["energy"][j] - 1.0).max()),
+                    whole_field_rel_l2_E_est=float(np.sqrt(((pE - gb["projE"][j][0]) ** 2).mean()
+                                                           / (gb["projE"][j][0] ** 2).mean())),
+                    whole_field_rel_l2_H_est=max(float(np.sqrt(((pH[c] - gb["projH"][j][c]) ** 2).mean()
+                                                               / (gb["projH"][j][c] ** 2).mean())) for c in range(2)))
+                worst = {key: max(worst[key], vals[key]) for key in worst}
+            acc_b.update(worst)
+            acc_b["oracle_reference"] = ("FP64 CPU oracle single-field runs of these pulses "
+                                         "(tests/golden/batch64_250k.npz); worst of the four fields")
         del sb, stb
         torch.cuda.empty_cache()
         # one field on the same nodes and weights: 64 such runs are the alternative
@@ -617,7 +649,8 @@ def main():
                              "variant": vb,
                              "steps": kb, "node_steps_per_s": wb.N * kb / tb,
                              "alg_bytes_per_field_node_step": 50.0,
-                             "hbm_frac_at_50B": round(wb.N * 64 * kb / tb * 50.0 / (HBM_PEAK_GBS * 1e9), 4)}
+                             "hbm_frac_at_50B": round(wb.N * 64 * kb / tb * 50.0 / (HBM_PEAK_GBS * 1e9), 4),
+                             "vs_oracle": acc_b}
         log(f"batched: {extras['batched']}")
         torch.cuda.empty_cache()
     if "bf16" in legs:
