@@ -362,6 +362,21 @@ int rbffd_energy_static(const rbffd_plan* plan, const void* E, const void* Ha, c
  * plan; reps = timed repetitions per variant.  Optional: plans start with a
  * default that is valid everywhere. */
 int rbffd_autotune(rbffd_plan* plan, rbffd_fields* f, int32_t reps, void* stream);
+/* rbffd_autotune through a cache file of tuned variants, for callers that
+ * build plans of the same shape again (serving loops, repeated jobs).  The
+ * key is the device (architecture, compute-unit count) and the plan's shape
+ * (dimension, node counts, stencil sizes, K, field and weight precision,
+ * mode, polarisation, boundary, longest halo list).  Hit: the cached variant
+ * is set, nothing runs and f is left as it is (*hit = 1).  Miss: as
+ * rbffd_autotune (f advanced by the trial steps), then one line
+ * "rbffd-variant <key> <block> <xcd> <lds> <persist>" is appended to
+ * cache_path (created if absent; *hit = 0).  Lines that do not parse, and
+ * cached variants rbffd_set_variant refuses, are ignored; the last line for
+ * a key wins.  hit may be NULL.  RBFFD_EINVAL for a null argument or a file
+ * that cannot be written; concurrent writers may interleave lines, which
+ * the reader then ignores. */
+int rbffd_autotune_cached(rbffd_plan* plan, rbffd_fields* f, int32_t reps, const char* cache_path, int32_t* hit,
+                          void* stream);
 /* Active launch variant of the step kernels, packed as block | xcd << 16 |
  * lds << 17 | persist << 20 (block = threads per workgroup of the unstaged
  * kernels, xcd = XCD-aware workgroup order, lds = 0 global gathers, 1 LDS-staged

@@ -96,6 +96,8 @@ PROTOTYPES = {
                                 C.c_void_p]),
     "rbffd_energy_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rbffd_autotune": (C.c_int, [C.c_void_p, C.POINTER(Fields), C.c_int32, C.c_void_p]),
+    "rbffd_autotune_cached": (C.c_int, [C.c_void_p, C.POINTER(Fields), C.c_int32, C.c_char_p,
+                                        C.POINTER(C.c_int32), C.c_void_p]),
     "rbffd_get_variant": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "rbffd_set_variant": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "rbffd_set_field_hv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

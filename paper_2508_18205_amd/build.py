@@ -17,7 +17,7 @@ OUT = os.path.join(PKG, "librbffd.so")
 BUILD = os.path.join(PKG, "_build")
 ARCH = os.environ.get("RBFFD_ARCH", "gfx950")
 
-SOURCES = ["plan.hip", "setup.hip", "step.hip", "batched.hip", "adjoint.hip", "probe.hip"]
+SOURCES = ["plan.hip", "setup.hip", "step.hip", "batched.hip", "adjoint.hip", "probe.hip", "tunecache.hip"]
 
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -8,6 +8,7 @@ library's own permutation kernel.
 """
 import ctypes as C
 import math
+import os
 
 import numpy as np
 import torch
@@ -369,12 +370,20 @@ class Solver:
               self.plan, "rbffd_compare")
         return out.cpu().numpy().reshape(nc, 3)
 
-    def autotune(self, st, reps=20):
+    def autotune(self, st, reps=20, cache=None):
+        """Tune the launch variant (rbffd_autotune), or with ``cache`` (a file
+        path) look it up there first (rbffd_autotune_cached); the attribute
+        ``tune_hit`` tells whether the cache held it."""
         f = st.struct()
-        check(self.lib.rbffd_autotune(self.plan, C.byref(f), int(reps), self.stream()), self.plan, "autotune")
+        if cache is None:
+            check(self.lib.rbffd_autotune(self.plan, C.byref(f), int(reps), self.stream()), self.plan, "autotune")
+            self.tune_hit = False
+        else:
+            hit = C.c_int32(0)
+            check(self.lib.rbffd_autotune_cached(self.plan, C.byref(f), int(reps), os.fsencode(cache), C.byref(hit),
+                                                 self.stream()), self.plan, "autotune_cached")
+            self.tune_hit = bool(hit.value)
         st.cur = f.cur
-        v = C.c_int32()
-        self.lib.rbffd_get_variant(self.plan, C.byref(v))
         return self.variant()
 
     def set_variant(self, block=256, xcd=1, lds=1, persist=8):

@@ -359,6 +359,41 @@ def test_staged_and_global_kernels_agree(case):
         assert (out[0][0] == o[0]).all() and (out[0][1] == o[1]).all()
 
 
+def test_autotune_cache(tmp_path):
+    # the tuner's choice kept in a cache file: a miss tunes and appends one
+    # line; a plan of the same shape then hits (the variant is set, the
+    # fields are left as they are); lines that do not parse are ignored; a
+    # cached variant the plan refuses is ignored and tuned again; a plan of
+    # another shape misses
+    _announce("autotune cache")
+    cache = str(tmp_path / "variants.txt")
+
+    def entries():
+        return [x for x in open(cache).read().splitlines() if x.startswith("rbffd-variant ")]
+
+    w = configs.tm_cavity_2d(n_side=41, chat=1e-3)
+    s = Solver.from_workload(w, precision="f32")
+    v1 = s.autotune(s.state(w.E0, w.H0), reps=3, cache=cache)
+    assert not s.tune_hit and len(entries()) == 1
+    with open(cache, "a") as fh:
+        fh.write("not a cache line\nrbffd-variant\n")
+    s2 = Solver.from_workload(w, precision="f32")
+    s2.set_variant(block=64, xcd=0, lds=0)
+    st2 = s2.state(w.E0, w.H0)
+    E0 = s2.E_original(st2)
+    v2 = s2.autotune(st2, reps=3, cache=cache)
+    assert s2.tune_hit and v2 == v1 and np.array_equal(s2.E_original(st2), E0)
+    key = entries()[0].split()[1]
+    with open(cache, "a") as fh:
+        fh.write(f"rbffd-variant {key} 1000 1 1 8\n")
+    s3 = Solver.from_workload(w, precision="f32")
+    s3.autotune(s3.state(w.E0, w.H0), reps=3, cache=cache)
+    assert not s3.tune_hit and len(entries()) == 3
+    s4 = Solver.from_workload(w, precision="f64")
+    s4.autotune(s4.state(w.E0, w.H0), reps=3, cache=cache)
+    assert not s4.tune_hit and len(entries()) == 4 and entries()[-1].split()[1] != key
+
+
 def test_rcm_order_bit_exact():
     _announce("RCM order")
     xyz, flags, h = nodes.jittered_grid((23, 19), seed=29)
